@@ -1,0 +1,144 @@
+#!/usr/bin/env python3
+"""Benchmark: cell-updates/s of the MUSCL-HLLC-RK2 step on one MI355X.
+
+Workload (default ``config2``): the 10 km x 2 km meandering channel,
+1582 x 316 quads = 999,824 triangles, bumpy bed with dry banks, Manning n in
+[0.02, 0.05], 500 m^3/s inflow, fixed-stage outflow, FP32 state, minmod
+MUSCL + hydrostatic reconstruction + HLLC + Manning + SSP-RK2, CFL 0.45.
+One "step" is one full time step: both RK2 stages (reconstruction, fluxes,
+sources, friction, update) and the on-device CFL reduction for the next step;
+the state stays in HBM for the whole timed region.
+
+Prints one JSON line.  ``value`` = owned cells x steps / wall seconds.
+``roofline`` prices the stage kernel (the only kernel of the step) against
+8 TB/s with the per-cell algorithmic bytes of the stored-geometry design; its
+launch time comes from HIP events recorded on the library's stream.
+``cpu_baseline`` times the serial FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per cell and launch of the FP32 stage kernel (the
+# stored-geometry layout): stage 1 reads neighbours (16), state (16), cell
+# geometry (16), half-edge geometry (48) and MUSCL distances (48) and writes
+# the state (16): 160 B; stage 2 also reads U^n (16): 176 B.
+BYTES_STAGE1 = 160
+BYTES_STAGE2 = 176
+
+
+def workload(name):
+    from swe_inputs import config1, config2, config3
+    if name == "config1":
+        return config1(), dict(precision=1, scheme=0, integrator=0, limiter=0)
+    if name == "config2":
+        return config2(), dict(precision=0, scheme=1, integrator=1, limiter=0)
+    if name == "config3_full":
+        return config3(), dict(precision=0, scheme=1, integrator=1, limiter=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(sc, kw, seconds):
+    """Serial FP64 oracle on the same mesh: as many steps as fit in about
+    ``seconds`` (at least one), one core."""
+    from oracle import oracle as O
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, scheme=kw["scheme"], integrator=kw["integrator"],
+                          limiter=kw["limiter"])
+    h, hu, hv, t = sc.h, sc.hu, sc.hv, 0.0
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        h, hu, hv, t, _ = M.run(p, h, hu, hv, 1, t=t)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return dict(value=sc.n_cells * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{sc.name}: {sc.n_cells} cells, first {steps} steps, serial FP64 "
+                       f"({el:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1200)
+    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on exactly one GPU: the path measured is one GPU's "
+              "sub-domain (multi-GPU exchange is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2307_16758_amd import swe
+    from paper_2307_16758_amd.problem import prepare_scenario
+
+    sc, kw = workload(args.workload)
+    pr = prepare_scenario(sc)
+    s = swe.Solver(device=0, block=args.block, **kw)
+    s.mesh_upload(pr.mesh)
+    if sc.hydrograph is not None:
+        s.set_bc_series(*sc.hydrograph)
+    l2g = pr.sub.l2g
+    s.set_state(sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    n_owned = pr.sub.n_owned
+
+    s.step(args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = s.last_step_ms()           # HIP events around the timed steps, library stream
+    health = s.health()
+
+    rk2 = kw["integrator"] == 1
+    launches = args.steps * (2 if rk2 else 1)
+    avg_launch_s = gpu_ms * 1e-3 / launches
+    per_launch_bytes = ((BYTES_STAGE1 + BYTES_STAGE2) / 2 if rk2 else BYTES_STAGE1) * n_owned
+    if kw["precision"] == 1:
+        per_launch_bytes *= 2
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    out = {
+        "metric": "cell-updates/s (MUSCL-HLLC, FP32, 1 GPU)",
+        "value": n_owned * args.steps / wall,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if kw["precision"] == 0 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {sc.name}, {n_owned} triangles, "
+                               f"{'MUSCL-HLLC-RK2' if rk2 else 'HLLC-Euler'}",
+                   "cells": n_owned, "parallelism": "single GPU, single domain"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage", "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_launch": per_launch_bytes},
+        "health_bits": health,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * swe.h -- C ABI of the MI355X shallow-water finite-volume library (libswe.so).
+ *
+ * Method: Delmas & Soulaimani, "Parallel high-order resolution of the
+ * Shallow-water equations on real large-scale meshes with complex
+ * bathymetries".  One explicit time step of the 2D shallow-water equations on
+ * one sub-domain of an unstructured triangle mesh with k layers of ghost
+ * cells: MUSCL reconstruction with a slope limiter (Sec. 6.2.3), hydrostatic
+ * reconstruction with wet/dry treatment, HLLC (Sec. 6.2.1) or WAF
+ * (Sec. 6.2.2) fluxes, the cell sum of eq. (vlap2) with bed source, Manning
+ * friction and Euler / SSP-RK2 update (Sec. 6.1), the CFL step of Sec. 6.1,
+ * and the on-device packing of the send buffers of Sec. 6.4 (receives land in
+ * place because ghosts are numbered contiguously per owner, Sec. 3.3).
+ *
+ * Conventions
+ *  - Every function returns an int status: SWE_OK (0) or a negative SWE_ERR_*.
+ *    No exception crosses the ABI.  swe_last_error() gives a message for the
+ *    last failure on a context; swe_strerror() names a code.
+ *  - Host arrays passed in are copied; the caller keeps ownership.
+ *  - Device pointers (where == SWE_DEVICE) are borrowed for the duration of
+ *    the call only and must be valid on the context's device and ordered with
+ *    the context's stream (the library synchronises the stream before it
+ *    returns from any call that reads or writes caller memory).
+ *  - All buffers the library allocates are owned by the context and released
+ *    by swe_destroy().
+ *  - Work is issued on the context's stream (a stream the library creates,
+ *    default priority, non-blocking).  swe_step() is asynchronous; health
+ *    errors (non-finite values, negative depths) are reported at the next
+ *    synchronising call (swe_sync, swe_time, swe_read_state, swe_health).
+ *  - One context per host thread; calls on one context are not thread-safe.
+ *  - Cell layout: SoA arrays of n_total cells; the owned cells come first
+ *    (indices [0, n_owned)), ghost cells after them, in one contiguous block
+ *    per peer (see swe_subdomain_*).
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_ABI_VERSION 1
+
+/* status codes */
+#define SWE_OK 0
+#define SWE_ERR_ARG -1            /* bad argument (null pointer, bad size, bad enum) */
+#define SWE_ERR_MESH -2           /* mesh fails validation at upload */
+#define SWE_ERR_STATE -3          /* state missing or invalid (e.g. negative depth given) */
+#define SWE_ERR_NONFINITE -4      /* a NaN/Inf appeared in the state while stepping */
+#define SWE_ERR_NEGATIVE_DEPTH -5 /* a depth below -eps appeared while stepping */
+#define SWE_ERR_DEVICE -6         /* HIP runtime error */
+#define SWE_ERR_OOM -7            /* device allocation failed */
+#define SWE_ERR_UNSUPPORTED -8    /* option not available in this build */
+
+/* enums */
+#define SWE_F32 0
+#define SWE_F64 1
+#define SWE_HLLC1 0       /* first-order HLLC (Sec. 6.2.1) */
+#define SWE_MUSCL 1       /* MUSCL reconstruction + HLLC (Sec. 6.2.3) */
+#define SWE_WAF 2         /* weighted average flux (Sec. 6.2.2) */
+#define SWE_EULER 0
+#define SWE_RK2 1         /* two-stage SSP Runge-Kutta (Heun) */
+#define SWE_MINMOD 0      /* beta = 1 limiter (MINBEE) */
+#define SWE_SUPERBEE 1    /* beta = 2 limiter */
+#define SWE_VANALBADA 2
+#define SWE_LEARNED 3     /* per-half-edge network phi in [0,1] x central slope */
+#define SWE_ZEROSLOPE 4   /* slopes forced to zero (first order through the MUSCL path) */
+#define SWE_WAF_SUPERBEE 0
+#define SWE_WAF_GODUNOV 1   /* A = 1: WAF reduces to HLLC */
+#define SWE_WAF_UNLIMITED 2 /* A = |c| */
+#define SWE_HOST 0
+#define SWE_DEVICE 1
+
+/* boundary tags in cell_nbr (a negative entry instead of a neighbour index) */
+#define SWE_BC_WALL -1
+#define SWE_BC_TRANSMISSIVE -2
+#define SWE_BC_INFLOW -3
+#define SWE_BC_OUTFLOW -4   /* fixed stage */
+#define SWE_BC_HALO -5      /* edge cut by the end of the ghost layers: transmissive */
+
+/* health bits (swe_health) */
+#define SWE_HEALTH_NONFINITE 1
+#define SWE_HEALTH_NEGDEPTH 2
+#define SWE_HEALTH_CLIPPED 4   /* a depth in [-eps, 0) was set to 0 */
+
+typedef struct swe_ctx swe_ctx;
+typedef struct swe_subdomain swe_subdomain;
+
+/* Solver options.  Defaults from swe_config_default(). */
+typedef struct {
+    int abi_version;   /* SWE_ABI_VERSION */
+    int precision;     /* SWE_F32 | SWE_F64: arithmetic and state type */
+    int scheme;        /* SWE_HLLC1 | SWE_MUSCL | SWE_WAF */
+    int integrator;    /* SWE_EULER | SWE_RK2 */
+    int limiter;       /* SWE_MINMOD | SWE_SUPERBEE | SWE_VANALBADA | SWE_LEARNED | SWE_ZEROSLOPE */
+    int waf_limiter;   /* SWE_WAF_* */
+    int cfl_rule;      /* 0: min_i R_i/lambda_i;  1: min_i R_i / max_i lambda_i (printed form) */
+    int device;        /* HIP device ordinal */
+    double g;          /* gravity, default 9.81 */
+    double cfl;        /* default 0.45 */
+    double eps;        /* wet/dry threshold [m], default 1e-6 */
+    double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
+    int block;         /* threads per block for the cell kernels (0: autotuned/default) */
+    int reserved[7];
+} swe_config;
+
+/* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).
+ * Cell connectivity is the fixed-degree CSR of triangles: cell i owns the
+ * three entries [3i, 3i+3) of cell_nodes and cell_nbr; local edge m of cell i
+ * joins cell_nodes[3i+m] and cell_nodes[3i+(m+1)%3]. */
+typedef struct {
+    int32_t n_nodes;
+    const double *node_xy;      /* [2*n_nodes] x,y */
+    int32_t n_owned, n_total;   /* ghosts are [n_owned, n_total) */
+    const int32_t *cell_nodes;  /* [3*n_total] counter-clockwise */
+    const int64_t *cell_gid;    /* [n_total] global ids: each edge flux is computed with
+                                   L = the cell of smaller gid (canonical orientation) */
+    const int32_t *cell_nbr;    /* [3*n_total] local neighbour index, or a SWE_BC_* tag */
+    const double *cell_b;       /* [n_total] bed elevation */
+    const double *cell_manning; /* [n_total] Manning n (0: frictionless) */
+    int32_t n_peers;
+    const int32_t *peer_part;   /* [n_peers] ascending part ids (informative) */
+    const int32_t *recv_off;    /* [n_peers+1]: ghost block q = [n_owned+recv_off[q], n_owned+recv_off[q+1]) */
+    const int32_t *send_off;    /* [n_peers+1] */
+    const int32_t *send_idx;    /* [send_off[n_peers]] local owned cells, per peer in the
+                                   receiver's order */
+    double inflow_q;            /* total inflow discharge [m^3/s] on SWE_BC_INFLOW edges */
+    double inflow_length;       /* total length of the inflow edges of the WHOLE mesh
+                                   (<= 0: computed from this mesh's owned cells) */
+    double outflow_stage;       /* free-surface elevation on SWE_BC_OUTFLOW edges */
+} swe_mesh;
+
+/* ---- context ---------------------------------------------------------- */
+void swe_config_default(swe_config *cfg);
+int swe_create(const swe_config *cfg, swe_ctx **out);
+void swe_destroy(swe_ctx *ctx);
+const char *swe_last_error(const swe_ctx *ctx);
+const char *swe_strerror(int code);
+
+/* Copy a mesh to the device: validation (counter-clockwise cells, symmetric
+ * neighbours, ghost and send ranges in bounds), geometry (areas, normals,
+ * lengths, inscribed radii, MUSCL distances) and the device layout.
+ * Replaces any previous mesh; the state must be set again afterwards. */
+int swe_mesh_upload(swe_ctx *ctx, const swe_mesh *mesh);
+
+/* Inflow hydrograph Q(t), piecewise linear through n points (clamped at the
+ * ends), evaluated at each stage's time.  n = 0 restores the constant Q. */
+int swe_set_bc_series(swe_ctx *ctx, int n, const double *t, const double *q);
+
+/* State of all n_total cells in the context's precision (float or double),
+ * three SoA arrays.  set_state also sets the time and computes the CFL step
+ * of the first step.  Negative or non-finite depths are rejected. */
+int swe_set_state(swe_ctx *ctx, const void *h, const void *hu, const void *hv, int where,
+                  double t);
+int swe_read_state(swe_ctx *ctx, void *h, void *hu, void *hv, int where);
+
+/* n_steps explicit steps, asynchronous on the context's stream.
+ * dt_fixed > 0: every step uses that dt; otherwise the CFL step of Sec. 6.1
+ * (computed on the device from the owned cells, never copied to the host). */
+int swe_step(swe_ctx *ctx, int n_steps, double dt_fixed);
+
+int swe_sync(swe_ctx *ctx);                 /* wait + report health */
+int swe_time(swe_ctx *ctx, double *t);      /* simulated time (syncs) */
+int swe_local_dt(swe_ctx *ctx, double *dt); /* CFL step of the current state (syncs) */
+int swe_health(swe_ctx *ctx, int *bits);    /* SWE_HEALTH_* bits since the last set_state */
+
+/* Gather the owned cells listed in send_idx into dev_sendbuf, laid out
+ * [3][n_send] (h, hu, hv; context precision), in CSR order of the peers. */
+int swe_pack_ghosts(swe_ctx *ctx, void *dev_sendbuf);
+/* Copy dev_recvbuf, laid out [3][n_total - n_owned], into the ghost cells. */
+int swe_unpack_ghosts(swe_ctx *ctx, const void *dev_recvbuf);
+int swe_ghost_sizes(const swe_ctx *ctx, int32_t *n_send, int32_t *n_ghost);
+
+/* Wall time of the kernels of the last swe_step call (ms, measured with HIP
+ * events on the context stream; syncs). */
+int swe_last_step_ms(swe_ctx *ctx, float *ms);
+
+/* ---- host mesh toolkit (Sec. 3.1 - 3.3), CPU only ---------------------- */
+/* Dual graph: cell across each local edge, -1 where none (global numbering).
+ * Fails with SWE_ERR_MESH for an edge shared by more than two cells or by two
+ * cells that traverse it in the same direction. */
+int swe_dual_graph(int32_t n_nodes, int32_t n_cells, const int32_t *cell_nodes, int32_t *nbr);
+/* Greedy breadth-first partition into P parts of sizes floor(n/P)+(p < n%P). */
+int swe_partition_bfs(int32_t n_cells, const int32_t *nbr, int32_t P, int32_t *part);
+/* Total length of the edges whose boundary tag bc[3*i+m] equals tag (for
+ * the inflow length of a whole mesh before it is split into sub-domains). */
+int swe_edge_length_sum(int32_t n_nodes, const double *node_xy, int32_t n_cells,
+                        const int32_t *cell_nodes, const int8_t *bc, int32_t tag, double *out);
+/* 32-bit Morton key of each cell centroid (16 bits per axis, x on even bits,
+ * over the bounding box of all centroids). */
+int swe_morton_keys(int32_t n_nodes, const double *node_xy, int32_t n_cells,
+                    const int32_t *cell_nodes, uint32_t *key);
+/* Part p with k ghost layers: local numbering (send cells, interior cells,
+ * ghost blocks per peer), local neighbour table with boundary tags
+ * (bc[3*n_cells] gives the tag of each edge that has no neighbour), receive
+ * ranges and send lists.  The object owns its arrays. */
+int swe_subdomain_build(int32_t n_nodes, const double *node_xy, int32_t n_cells,
+                        const int32_t *cell_nodes, const int32_t *nbr, const int8_t *bc,
+                        const int32_t *part, int32_t P, int32_t p, int32_t k,
+                        swe_subdomain **out);
+typedef struct {
+    int32_t n_owned, n_total, n_peers, n_send;
+    const int32_t *l2g;       /* [n_total] global id of each local cell */
+    const int32_t *layer;     /* [n_total] 0 owned, j for ghost layer j */
+    const int32_t *owner;     /* [n_total] part of each local cell */
+    const int32_t *nbr;       /* [3*n_total] local neighbour or SWE_BC_* tag */
+    const int32_t *peers;     /* [n_peers] */
+    const int32_t *recv_off;  /* [n_peers+1] */
+    const int32_t *send_off;  /* [n_peers+1] */
+    const int32_t *send_idx;  /* [n_send] */
+} swe_subdomain_view;
+int swe_subdomain_view_get(const swe_subdomain *sd, swe_subdomain_view *view);
+void swe_subdomain_free(swe_subdomain *sd);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWE_H */

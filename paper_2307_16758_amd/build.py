@@ -1,0 +1,45 @@
+"""Build libswe.so for gfx950 in-tree: g++ for the host mesh toolkit,
+hipcc for the device runtime.  ``python paper_2307_16758_amd/build.py``
+(run as a script: importing the package itself needs the built library)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libswe.so")
+ARCH = os.environ.get("SWE_OFFLOAD_ARCH", "gfx950")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+             # no packed FP32 instructions anywhere in the device code
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-result"]
+
+
+def run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    obj = os.path.join(HERE, "_build", "swe_host.o")
+    run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
+         os.path.join(CSRC, "swe_host.cpp"), "-o", obj])
+    objs = [obj]
+    for src in ("swe_device.hip", "swe_mlp.hip"):
+        o = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
+        run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
+    tmp = LIB + f".tmp{os.getpid()}"
+    run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,1004 @@
+// Device runtime of libswe.so: the fused stage kernel of the explicit
+// shallow-water step (Delmas & Soulaimani, Sec. 6.1 - 6.2), the CFL
+// reduction, ghost packing (Sec. 6.4) and the C ABI of include/swe.h.
+//
+// One thread per cell.  Cells are numbered in Morton order (send cells
+// first), so a block's 1- and 2-ring gathers stay in the XCD's L2; blocks are
+// remapped so that each of the 8 XCDs sweeps one contiguous range of tiles.
+// Every interior edge flux is evaluated in the canonical orientation (L = the
+// cell of smaller global id, L's normal) by both of its cells with identical
+// operands, so the two contributions cancel bitwise; cell sums run over the
+// local edges 0, 1, 2 in order; there are no atomics on the state, and the
+// results are deterministic run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "swe_internal.h"
+#include "swe_kernels.h"
+
+using namespace swe;
+
+namespace {
+
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;  // +inf as double bits
+
+__device__ __forceinline__ unsigned long long dbits(double x)
+{
+    return (unsigned long long)__double_as_longlong(x);
+}
+__device__ __forceinline__ double bitsd(unsigned long long b)
+{
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ int xcd_tile(int bid, int nb)
+{
+    // blocks are dealt to the 8 XCDs round-robin; give XCD x one contiguous
+    // range of tiles so that neighbouring tiles share its L2
+    const int x = bid & 7, i = bid >> 3, base = nb >> 3, rem = nb & 7;
+    return x * base + (x < rem ? x : rem) + i;
+}
+
+__device__ __forceinline__ double step_dt(const Clock &c, double cfl, double dt_max, int rule,
+                                          double dt_fixed)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    if (c.ratio_min == kInfBits) return dt_max > 0.0 ? dt_max : 0.0;  // nothing wet
+    double dt = rule == 1 ? cfl * bitsd(c.rad_min) / bitsd(c.lam_max) : cfl * bitsd(c.ratio_min);
+    if (dt_max > 0.0 && dt > dt_max) dt = dt_max;
+    return dt;
+}
+
+__device__ __forceinline__ double inflow_at(const ScenParams &s, const double *ts, const double *qs,
+                                            double t)
+{
+    if (s.series_n <= 0) return s.inflow_q;
+    const double *T = ts + s.series_off, *Q = qs + s.series_off;
+    const int n = s.series_n;
+    if (t <= T[0]) return Q[0];
+    if (t >= T[n - 1]) return Q[n - 1];
+    for (int i = 0; i + 1 < n; ++i)
+        if (t <= T[i + 1]) return Q[i] + (Q[i + 1] - Q[i]) * (t - T[i]) / (T[i + 1] - T[i]);
+    return Q[n - 1];
+}
+
+template <typename T> struct StageArgs {
+    using T4 = typename V4<T>::type;
+    int n, n_scen;
+    const int4 *nbr;
+    const T4 *cell, *he_geo, *he_dist;
+    const T4 *Uin, *U0;
+    T4 *Uout;
+    Clock *clock;
+    const ScenParams *scen;
+    const double *ser_t, *ser_q;
+    const float *phi;
+    int *health;
+    T g, eps;
+    double cfl, dt_max, dt_fixed;
+    int slot_cur, slot_next, slot_reset;
+    int kind;  // 0: Euler step, 1: first RK2 stage, 2: second RK2 stage (+ average)
+    int cfl_rule;
+};
+
+// Boundary flux of Sec. 6.1 in the global frame.
+template <typename T, typename T4>
+__device__ __forceinline__ void boundary_flux(int tag, const T4 &Uc, T nx, T ny, T g, T eps, T q_in,
+                                              T stage, T G[3])
+{
+    const T h = Uc.x;
+    T U[3] = {h, Uc.y * nx + Uc.z * ny, -Uc.y * ny + Uc.z * nx};
+    T F[3];
+    if (tag == kBcWall) {
+        F[0] = T(0); F[1] = T(0.5) * g * h * h; F[2] = T(0);
+    } else if (tag == kBcInflow) {
+        const T hl = tmax(h, T(1e-3));
+        F[0] = -q_in; F[1] = q_in * q_in / hl + T(0.5) * g * h * h; F[2] = T(0);
+    } else if (tag == kBcOutflow) {
+        const T hg = tmax(T(0), stage - Uc.w);
+        const T un = h > eps ? U[1] / h : T(0), ut = h > eps ? U[2] / h : T(0);
+        T UG[3] = {hg, hg * un, hg * ut};
+        flux_hllc(g, eps, U, UG, F);
+    } else {
+        flux_hllc(g, eps, U, U, F);
+    }
+    G[0] = F[0];
+    G[1] = F[1] * nx - F[2] * ny;
+    G[2] = F[1] * ny + F[2] * nx;
+}
+
+template <typename T, typename T4>
+__device__ __forceinline__ T tangential(const T4 &U, T nx, T ny, T eps)
+{
+    return U.x > eps ? (-U.y * ny + U.z * nx) / U.x : T(0);
+}
+
+// upwind mean of eta and v (L frame) over a cell's two upwind neighbours; a
+// missing or dry neighbour does not count
+template <typename T, typename T4>
+__device__ __forceinline__ bool waf_upwind(const T4 &Ua, bool ha, const T4 &Ub, bool hb, T nx,
+                                           T ny, T eps, T &e, T &v)
+{
+    ha = ha && Ua.x > eps;
+    hb = hb && Ub.x > eps;
+    if (ha && hb) {
+        e = T(0.5) * ((Ua.x + Ua.w) + (Ub.x + Ub.w));
+        v = T(0.5) * (tangential(Ua, nx, ny, eps) + tangential(Ub, nx, ny, eps));
+    } else if (ha) {
+        e = Ua.x + Ua.w; v = tangential(Ua, nx, ny, eps);
+    } else if (hb) {
+        e = Ub.x + Ub.w; v = tangential(Ub, nx, ny, eps);
+    } else {
+        e = T(0); v = T(0);
+    }
+    return ha || hb;
+}
+
+template <typename T, int SCHEME, int LIM, int WAFM>
+__global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
+{
+    using T4 = typename V4<T>::type;
+    const int bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = bid * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0) {
+        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
+            if (a.kind != 2) {  // first kernel of the step: clear the slot of step + 2
+                Clock &r = a.clock[3 * s + a.slot_reset];
+                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
+            }
+            if (a.kind != 1) {  // last kernel of the step: advance the time
+                const Clock cur = a.clock[3 * s + a.slot_cur];
+                a.clock[3 * s + a.slot_next].t =
+                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
+            }
+        }
+    }
+    double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
+    int scen = -1;
+    if (c < a.n) {
+        const int4 nb4 = a.nbr[c];
+        const unsigned word = (unsigned)nb4.w;
+        const int s = (int)(word >> kScenShift);
+        const Clock ck = a.clock[3 * s + a.slot_cur];
+        const double dtd = step_dt(ck, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
+        const T dt = T(dtd);
+        const T g = a.g, eps = a.eps;
+        const T4 Uc = a.Uin[c];
+        const T4 cg = a.cell[c];
+        const int nbr[3] = {nb4.x, nb4.y, nb4.z};
+        T4 Un[3];
+        bool hn[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            hn[m] = nbr[m] >= 0;
+            Un[m] = hn[m] ? a.Uin[nbr[m]] : Uc;
+        }
+        T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T4 ge = a.he_geo[3 * c + m];
+            const T nx = ge.x, ny = ge.y, L = ge.z;
+            const int k = nbr[m];
+            if (k < 0) {
+                const ScenParams sp = a.scen[s];
+                const double t_st = ck.t + (a.kind == 2 ? dtd : 0.0);
+                const T q_in = k == kBcInflow
+                                   ? T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len)
+                                   : T(0);
+                T G[3];
+                boundary_flux<T, T4>(k, Uc, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
+                acc0 += L * G[0];
+                acc1 += L * G[1];
+                acc2 += L * G[2];
+                continue;
+            }
+            const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+            const int jb = (word >> (2 * m)) & 3;
+            T4 zero4;
+            zero4.x = T(0); zero4.y = T(0); zero4.z = T(0); zero4.w = T(0);
+            T4 Uka = Uc, Ukb = Uc;
+            bool hka = false, hkb = false;
+            if (SCHEME != kHLLC1) {
+                const int4 nk = a.nbr[k];
+                const int nk3[3] = {nk.x, nk.y, nk.z};
+                const int ka = nk3[(jb + 1) % 3], kb = nk3[(jb + 2) % 3];
+                hka = ka >= 0;
+                hkb = kb >= 0;
+                if (hka) Uka = a.Uin[ka];
+                if (hkb) Ukb = a.Uin[kb];
+            }
+            T4 dc = zero4, dk = zero4;
+            T dmk = T(0);
+            float phic = 0.0f, phik = 0.0f;
+            if (SCHEME == kMUSCL) {
+                dc = a.he_dist[3 * c + m];
+                dk = a.he_dist[3 * k + jb];
+                dmk = a.he_geo[3 * k + jb].w;
+                if (LIM == kLearned) { phic = a.phi[3 * c + m]; phik = a.phi[3 * k + jb]; }
+            }
+            const Half<T> own = reconstruct<T, T4, SCHEME, LIM>(Uc, Un[m], Un[ma], hn[ma], Un[mb],
+                                                                hn[mb], nx, ny, ge.w, dc, phic, eps);
+            const Half<T> oth = reconstruct<T, T4, SCHEME, LIM>(Un[m], Uc, Uka, hka, Ukb, hkb, -nx,
+                                                                -ny, dmk, dk, phik, eps);
+            // hydrostatic reconstruction
+            const T be = tmax(own.b, oth.b);
+            const T hso = tmax(T(0), own.h + own.b - be);
+            const T hsk = tmax(T(0), oth.h + oth.b - be);
+            const bool isL = (word >> (6 + m)) & 1u;
+            T UL[3], UR[3];
+            T nLx, nLy;
+            if (isL) {
+                UL[0] = hso; UL[1] = hso * own.un; UL[2] = hso * own.ut;
+                UR[0] = hsk; UR[1] = -(hsk * oth.un); UR[2] = -(hsk * oth.ut);
+                nLx = nx; nLy = ny;
+            } else {
+                UL[0] = hsk; UL[1] = hsk * oth.un; UL[2] = hsk * oth.ut;
+                UR[0] = hso; UR[1] = -(hso * own.un); UR[2] = -(hso * own.ut);
+                nLx = -nx; nLy = -ny;
+            }
+            T F[3];
+            if (SCHEME == kWAF) {
+                const T4 dw = a.he_dist[3 * c + m];
+                const T4 &ULc = isL ? Uc : Un[m];
+                const T4 &URc = isL ? Un[m] : Uc;
+                WafIn<T> w;
+                w.eL = ULc.x + ULc.w; w.eR = URc.x + URc.w;
+                w.vL = tangential(ULc, nLx, nLy, eps);
+                w.vR = tangential(URc, nLx, nLy, eps);
+                T eo, vo, ek, vk;
+                const bool ho = waf_upwind(Un[ma], hn[ma], Un[mb], hn[mb], nLx, nLy, eps, eo, vo);
+                const bool hk = waf_upwind(Uka, hka, Ukb, hkb, nLx, nLy, eps, ek, vk);
+                if (isL) { w.eLu = eo; w.vLu = vo; w.hasLu = ho; w.eRu = ek; w.vRu = vk; w.hasRu = hk; }
+                else { w.eLu = ek; w.vLu = vk; w.hasLu = hk; w.eRu = eo; w.vRu = vo; w.hasRu = ho; }
+                flux_waf<T, WAFM>(g, eps, dt / dw.w, UL, UR, w, F);
+            } else {
+                flux_hllc(g, eps, UL, UR, F);
+            }
+            const T G0 = F[0];
+            const T G1 = F[1] * nLx - F[2] * nLy;
+            const T G2 = F[1] * nLy + F[2] * nLx;
+            const T sg = isL ? T(1) : T(-1);
+            const T p = T(0.5) * g * (own.h * own.h - hso * hso);  // side correction
+            const T sb = T(0.5) * g * (own.h + Uc.x) * (own.b - Uc.w);  // centred bed term
+            acc0 += L * (sg * G0);
+            acc1 += L * (sg * G1 + (p + sb) * nx);
+            acc2 += L * (sg * G2 + (p + sb) * ny);
+        }
+        T nh = Uc.x - dt * (acc0 * cg.x);
+        T nu = Uc.y - dt * (acc1 * cg.x);
+        T nv = Uc.z - dt * (acc2 * cg.x);
+        int flags = 0;
+        if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
+        if (nh < T(0)) {
+            flags |= nh < -eps ? kHealthNegDepth : kHealthClipped;
+            nh = T(0);
+        }
+        if (nh <= eps) {
+            nu = T(0); nv = T(0);
+        } else if (cg.z > T(0)) {  // Manning, point-implicit
+            const T sp = sqrt(nu * nu + nv * nv) / nh;
+            const T f = T(1) + dt * g * cg.z * sp / (nh * cbrt(nh));
+            nu /= f; nv /= f;
+        }
+        if (a.kind == 2) {  // SSP-RK2: average with U^n
+            const T4 U0c = a.U0[c];
+            nh = T(0.5) * (U0c.x + nh);
+            nu = T(0.5) * (U0c.y + nu);
+            nv = T(0.5) * (U0c.z + nv);
+            if (nh <= eps) { nu = T(0); nv = T(0); }
+        }
+        T4 out;
+        out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
+        a.Uout[c] = out;
+        if (flags) atomicOr(a.health, flags);
+        scen = s;
+        if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
+            const T u = nu / nh, v = nv / nh;
+            const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
+            ratio = double(cg.y / lm);
+            rad = double(cg.y);
+            lam = double(lm);
+        }
+    }
+    if (a.kind == 1) return;
+    // CFL reduction for the next step: wave-wide when the wave is one scenario
+    int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
+    for (int o = 32; o > 0; o >>= 1) {
+        smin = min(smin, __shfl_xor(smin, o));
+        smax = max(smax, __shfl_xor(smax, o));
+    }
+    if (smax < 0) return;
+    if (smin == smax) {
+        for (int o = 32; o > 0; o >>= 1) {
+            ratio = fmin(ratio, __shfl_xor(ratio, o));
+            rad = fmin(rad, __shfl_xor(rad, o));
+            lam = fmax(lam, __shfl_xor(lam, o));
+        }
+        if ((threadIdx.x & 63) == 0 && lam > 0.0) {
+            Clock &nx = a.clock[3 * smin + a.slot_next];
+            atomicMin(&nx.ratio_min, dbits(ratio));
+            atomicMin(&nx.rad_min, dbits(rad));
+            atomicMax(&nx.lam_max, dbits(lam));
+        }
+    } else if (scen >= 0 && lam > 0.0) {
+        Clock &nx = a.clock[3 * scen + a.slot_next];
+        atomicMin(&nx.ratio_min, dbits(ratio));
+        atomicMin(&nx.rad_min, dbits(rad));
+        atomicMax(&nx.lam_max, dbits(lam));
+    }
+}
+
+// CFL minima of the current state into one clock slot (after set_state).
+template <typename T>
+__global__ void k_cfl_init(int n, const int4 *nbr, const typename V4<T>::type *cell,
+                           const typename V4<T>::type *U, Clock *clock, int slot, T g, T eps)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const unsigned word = (unsigned)nbr[c].w;
+    if (!((word >> kOwnedBit) & 1u)) return;
+    const int s = (int)(word >> kScenShift);
+    const T h = U[c].x;
+    if (!(h > eps)) return;
+    const T u = U[c].y / h, v = U[c].z / h;
+    const T lm = sqrt(u * u + v * v) + sqrt(g * h);
+    Clock &k = clock[3 * s + slot];
+    atomicMin(&k.ratio_min, dbits(double(cell[c].y / lm)));
+    atomicMin(&k.rad_min, dbits(double(cell[c].y)));
+    atomicMax(&k.lam_max, dbits(double(lm)));
+}
+
+__global__ void k_clock_reset(Clock *clock, int n_scen, int slot, const double *t0, int set_t)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_scen) return;
+    Clock &k = clock[3 * s + slot];
+    k.ratio_min = kInfBits; k.rad_min = kInfBits; k.lam_max = 0ull;
+    if (set_t) k.t = t0[s];
+}
+
+template <typename T>
+__global__ void k_pack_state(int n, const T *h, const T *hu, const T *hv, const T *b,
+                             typename V4<T>::type *U, int *bad, T eps)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    typename V4<T>::type u;
+    u.x = h[c]; u.y = hu[c]; u.z = hv[c]; u.w = b[c];
+    if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z)) || u.x < T(0)) atomicOr(bad, 1);
+    U[c] = u;
+}
+
+template <typename T>
+__global__ void k_unpack_state(int n, const typename V4<T>::type *U, T *h, T *hu, T *hv)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const typename V4<T>::type u = U[c];
+    h[c] = u.x; hu[c] = u.y; hv[c] = u.z;
+}
+
+// Send buffer [3][n_send] from the owned cells listed in send_idx (Sec. 6.4).
+template <typename T>
+__global__ void k_pack_ghosts(int n_send, const int *send_idx, const typename V4<T>::type *U,
+                              T *buf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_send) return;
+    const typename V4<T>::type u = U[send_idx[i]];
+    buf[i] = u.x;
+    buf[n_send + i] = u.y;
+    buf[2 * n_send + i] = u.z;
+}
+
+// In-place receive: [3][n_ghost] into the contiguous ghost range.
+template <typename T>
+__global__ void k_unpack_ghosts(int n_owned, int n_ghost, const T *buf, typename V4<T>::type *U)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_ghost) return;
+    typename V4<T>::type u = U[n_owned + i];
+    u.x = buf[i]; u.y = buf[n_ghost + i]; u.z = buf[2 * n_ghost + i];
+    U[n_owned + i] = u;
+}
+
+__global__ void k_fill_int(int *p, int v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct swe_ctx {
+    swe_config cfg{};
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::string err;
+    bool has_mesh = false, has_state = false, ran = false;
+    int n_owned = 0, n_total = 0, n_scen = 1, n_send = 0, n_ghost = 0;
+    size_t tsize = 4;
+    // device buffers
+    void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
+    void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
+    float *phi = nullptr;
+    Clock *clock = nullptr;
+    ScenParams *scen = nullptr;
+    double *ser_t = nullptr, *ser_q = nullptr, *t0 = nullptr;
+    int *health = nullptr, *flag = nullptr, *send_idx = nullptr;
+    // host mirrors
+    std::vector<ScenParams> h_scen;
+    std::vector<double> h_ser_t, h_ser_q;
+    double computed_inflow_len = 0.0, given_inflow_len = 0.0;
+    long long step_count = 0;  // steps since set_state (selects clock slots and buffers)
+    int block = 256;
+    // graphs: chunk of kGraphSteps steps starting at a step index multiple of it
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = -1.0;
+    bool use_graphs = true;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 6;  // lcm of the clock-slot (3) and buffer (2) periods
+
+int set_err(swe_ctx *c, int code, const std::string &m)
+{
+    if (c) c->err = m;
+    return code;
+}
+
+#define HIP_OK(ctx, expr)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_err(ctx, e_ == hipErrorOutOfMemory ? SWE_ERR_OOM : SWE_ERR_DEVICE, \
+                           std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+void dfree(void *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+template <typename P> void dfree_t(P *&p)
+{
+    void *v = p;
+    dfree(v);
+    p = nullptr;
+}
+
+void release_mesh(swe_ctx *c)
+{
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    dfree(c->nbr); dfree(c->cell); dfree(c->he_geo); dfree(c->he_dist);
+    dfree(c->U[0]); dfree(c->U[1]); dfree(c->U1); dfree(c->tmp3); dfree(c->bed);
+    dfree_t(c->phi); dfree_t(c->clock); dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
+    dfree_t(c->t0); dfree_t(c->send_idx);
+    c->has_mesh = c->has_state = false;
+}
+
+template <typename T>
+void to_t(const std::vector<double> &src, std::vector<T> &dst)
+{
+    dst.resize(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = T(src[i]);
+}
+
+template <typename T>
+int upload_geometry(swe_ctx *c, const HostGeometry &g)
+{
+    const size_t n = c->n_total;
+    std::vector<T> tmp;
+    HIP_OK(c, hipMalloc(&c->nbr, 16 * n));
+    HIP_OK(c, hipMemcpy(c->nbr, g.nbr4.data(), 16 * n, hipMemcpyHostToDevice));
+    to_t(g.cell, tmp);
+    HIP_OK(c, hipMalloc(&c->cell, 4 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->cell, tmp.data(), 4 * sizeof(T) * n, hipMemcpyHostToDevice));
+    to_t(g.he_geo, tmp);
+    HIP_OK(c, hipMalloc(&c->he_geo, 12 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->he_geo, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
+    to_t(g.he_dist, tmp);
+    HIP_OK(c, hipMalloc(&c->he_dist, 12 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->he_dist, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
+    return SWE_OK;
+}
+
+int push_scenarios(swe_ctx *c)
+{
+    dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
+    HIP_OK(c, hipMalloc(&c->scen, sizeof(ScenParams) * c->h_scen.size()));
+    HIP_OK(c, hipMemcpy(c->scen, c->h_scen.data(), sizeof(ScenParams) * c->h_scen.size(),
+                        hipMemcpyHostToDevice));
+    const size_t ns = std::max<size_t>(1, c->h_ser_t.size());
+    HIP_OK(c, hipMalloc(&c->ser_t, sizeof(double) * ns));
+    HIP_OK(c, hipMalloc(&c->ser_q, sizeof(double) * ns));
+    if (!c->h_ser_t.empty()) {
+        HIP_OK(c, hipMemcpy(c->ser_t, c->h_ser_t.data(), sizeof(double) * c->h_ser_t.size(),
+                            hipMemcpyHostToDevice));
+        HIP_OK(c, hipMemcpy(c->ser_q, c->h_ser_q.data(), sizeof(double) * c->h_ser_q.size(),
+                            hipMemcpyHostToDevice));
+    }
+    return SWE_OK;
+}
+
+template <typename T> using KernelFn = void (*)(StageArgs<T>);
+
+template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm)
+{
+    if (scheme == kHLLC1) return k_stage<T, kHLLC1, kMinmod, 0>;
+    if (scheme == kWAF) {
+        if (wafm == kWafGodunov) return k_stage<T, kWAF, kMinmod, kWafGodunov>;
+        if (wafm == kWafUnlimited) return k_stage<T, kWAF, kMinmod, kWafUnlimited>;
+        return k_stage<T, kWAF, kMinmod, kWafSuperbee>;
+    }
+    switch (lim) {
+    case kSuperbee: return k_stage<T, kMUSCL, kSuperbee, 0>;
+    case kVanAlbada: return k_stage<T, kMUSCL, kVanAlbada, 0>;
+    case kLearned: return k_stage<T, kMUSCL, kLearned, 0>;
+    case kZeroSlope: return k_stage<T, kMUSCL, kZeroSlope, 0>;
+    default: return k_stage<T, kMUSCL, kMinmod, 0>;
+    }
+}
+
+template <typename T>
+int launch_step(swe_ctx *c, long long step, double dt_fixed)
+{
+    using T4 = typename V4<T>::type;
+    StageArgs<T> a{};
+    a.n = c->n_total;
+    a.n_scen = c->n_scen;
+    a.nbr = (const int4 *)c->nbr;
+    a.cell = (const T4 *)c->cell;
+    a.he_geo = (const T4 *)c->he_geo;
+    a.he_dist = (const T4 *)c->he_dist;
+    a.clock = c->clock;
+    a.scen = c->scen;
+    a.ser_t = c->ser_t;
+    a.ser_q = c->ser_q;
+    a.phi = c->phi;
+    a.health = c->health;
+    a.g = T(c->cfg.g);
+    a.eps = T(c->cfg.eps);
+    a.cfl = c->cfg.cfl;
+    a.dt_max = c->cfg.dt_max;
+    a.dt_fixed = dt_fixed;
+    a.cfl_rule = c->cfg.cfl_rule;
+    a.slot_cur = (int)(step % 3);
+    a.slot_next = (int)((step + 1) % 3);
+    a.slot_reset = (int)((step + 2) % 3);
+    KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter);
+    const int B = c->block;
+    const dim3 grid((c->n_total + B - 1) / B), blk(B);
+    T4 *Ucur = (T4 *)c->U[step & 1];
+    if (c->cfg.integrator == SWE_RK2) {
+        // stage 1: U^n -> U1;  stage 2: U1 -> U2, averaged with U^n in place
+        a.kind = 1; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U1;
+        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
+        a.kind = 2; a.Uin = (T4 *)c->U1; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
+        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
+    } else {
+        a.kind = 0; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
+        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
+    }
+    HIP_OK(c, hipGetLastError());
+    return SWE_OK;
+}
+
+int launch_step_any(swe_ctx *c, long long step, double dt_fixed)
+{
+    return c->cfg.precision == SWE_F64 ? launch_step<double>(c, step, dt_fixed)
+                                       : launch_step<float>(c, step, dt_fixed);
+}
+
+int health_status(swe_ctx *c)
+{
+    int bits = 0;
+    HIP_OK(c, hipMemcpy(&bits, c->health, sizeof(int), hipMemcpyDeviceToHost));
+    if (bits & kHealthNonfinite) return set_err(c, SWE_ERR_NONFINITE, "non-finite value in the state");
+    if (bits & kHealthNegDepth) return set_err(c, SWE_ERR_NEGATIVE_DEPTH, "depth below -eps in the state");
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void swe_config_default(swe_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->abi_version = SWE_ABI_VERSION;
+    cfg->precision = SWE_F32;
+    cfg->scheme = SWE_MUSCL;
+    cfg->integrator = SWE_RK2;
+    cfg->limiter = SWE_MINMOD;
+    cfg->waf_limiter = SWE_WAF_SUPERBEE;
+    cfg->g = 9.81;
+    cfg->cfl = 0.45;
+    cfg->eps = 1e-6;
+    cfg->dt_max = 0.0;
+}
+
+const char *swe_strerror(int code)
+{
+    switch (code) {
+    case SWE_OK: return "ok";
+    case SWE_ERR_ARG: return "invalid argument";
+    case SWE_ERR_MESH: return "invalid mesh";
+    case SWE_ERR_STATE: return "invalid or missing state";
+    case SWE_ERR_NONFINITE: return "non-finite state";
+    case SWE_ERR_NEGATIVE_DEPTH: return "negative depth";
+    case SWE_ERR_DEVICE: return "HIP runtime error";
+    case SWE_ERR_OOM: return "out of device memory";
+    case SWE_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown error";
+    }
+}
+
+const char *swe_last_error(const swe_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int swe_create(const swe_config *cfg, swe_ctx **out)
+{
+    if (!cfg || !out) return SWE_ERR_ARG;
+    *out = nullptr;
+    if (cfg->abi_version != SWE_ABI_VERSION) return SWE_ERR_ARG;
+    if (cfg->precision != SWE_F32 && cfg->precision != SWE_F64) return SWE_ERR_ARG;
+    if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
+        cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
+        cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
+        !(cfg->eps >= 0) || (cfg->block != 0 && (cfg->block % 64 || cfg->block > 256 || cfg->block < 64)))
+        return SWE_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_ERR_DEVICE;
+    if (cfg->device < 0 || cfg->device >= ndev) return SWE_ERR_ARG;
+    auto *c = new swe_ctx;
+    c->cfg = *cfg;
+    c->dev = cfg->device;
+    c->tsize = cfg->precision == SWE_F64 ? 8 : 4;
+    c->block = cfg->block ? cfg->block : 256;
+    if (hipSetDevice(c->dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipMalloc(&c->health, sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->flag, sizeof(int)) != hipSuccess) {
+        swe_destroy(c);
+        return SWE_ERR_DEVICE;
+    }
+    (void)hipMemset(c->health, 0, sizeof(int));
+    *out = c;
+    return SWE_OK;
+}
+
+void swe_destroy(swe_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->dev);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release_mesh(c);
+    dfree_t(c->health);
+    dfree_t(c->flag);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int swe_mesh_upload(swe_ctx *c, const swe_mesh *m)
+{
+    if (!c || !m) return set_err(c, SWE_ERR_ARG, "null argument");
+    HIP_OK(c, hipSetDevice(c->dev));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    HostGeometry g;
+    std::string msg;
+    int rc = prepare_geometry(*m, 0, g, msg);
+    if (rc != SWE_OK) return set_err(c, rc, msg);
+    // ghost exchange lists
+    const int n_ghost = m->n_total - m->n_owned;
+    if (m->n_peers < 0) return set_err(c, SWE_ERR_MESH, "n_peers < 0");
+    int n_send = 0;
+    if (m->n_peers > 0) {
+        if (!m->recv_off || !m->send_off || !m->send_idx)
+            return set_err(c, SWE_ERR_MESH, "ghost lists missing");
+        if (m->recv_off[0] != 0 || m->send_off[0] != 0 || m->recv_off[m->n_peers] != n_ghost)
+            return set_err(c, SWE_ERR_MESH, "receive ranges do not cover the ghost cells");
+        for (int j = 0; j < m->n_peers; ++j)
+            if (m->recv_off[j + 1] < m->recv_off[j] || m->send_off[j + 1] < m->send_off[j])
+                return set_err(c, SWE_ERR_MESH, "ghost offsets not ascending");
+        n_send = m->send_off[m->n_peers];
+        for (int i = 0; i < n_send; ++i)
+            if (m->send_idx[i] < 0 || m->send_idx[i] >= m->n_owned)
+                return set_err(c, SWE_ERR_MESH, "send index outside the owned cells");
+    } else if (n_ghost != 0) {
+        // ghosts without peers are allowed (halo kept by the caller) but cannot be received
+    }
+    release_mesh(c);
+    c->n_owned = m->n_owned;
+    c->n_total = m->n_total;
+    c->n_scen = 1;
+    c->n_send = n_send;
+    c->n_ghost = n_ghost;
+    rc = c->cfg.precision == SWE_F64 ? upload_geometry<double>(c, g) : upload_geometry<float>(c, g);
+    if (rc != SWE_OK) return rc;
+    const size_t n = c->n_total, ts = c->tsize;
+    HIP_OK(c, hipMalloc(&c->U[0], 4 * ts * n));
+    HIP_OK(c, hipMalloc(&c->U[1], 4 * ts * n));
+    HIP_OK(c, hipMalloc(&c->U1, 4 * ts * n));
+    HIP_OK(c, hipMalloc(&c->tmp3, 3 * ts * n));
+    HIP_OK(c, hipMalloc(&c->bed, ts * n));
+    HIP_OK(c, hipMalloc(&c->phi, sizeof(float) * 3 * n));
+    HIP_OK(c, hipMalloc(&c->clock, sizeof(Clock) * 3));
+    HIP_OK(c, hipMalloc(&c->t0, sizeof(double)));
+    if (ts == 8) {
+        HIP_OK(c, hipMemcpy(c->bed, m->cell_b, 8 * n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> bf(m->cell_b, m->cell_b + n);
+        HIP_OK(c, hipMemcpy(c->bed, bf.data(), 4 * n, hipMemcpyHostToDevice));
+    }
+    if (n_send > 0) {
+        HIP_OK(c, hipMalloc(&c->send_idx, sizeof(int) * n_send));
+        HIP_OK(c, hipMemcpy(c->send_idx, m->send_idx, sizeof(int) * n_send, hipMemcpyHostToDevice));
+    }
+    c->computed_inflow_len = g.inflow_length;
+    c->given_inflow_len = m->inflow_length;
+    const double L = m->inflow_length > 0 ? m->inflow_length : g.inflow_length;
+    ScenParams sp{};
+    sp.inflow_q = m->inflow_q;
+    sp.inv_inflow_len = L > 0 ? 1.0 / L : 0.0;
+    sp.outflow_stage = m->outflow_stage;
+    sp.series_off = 0;
+    sp.series_n = 0;
+    c->h_scen.assign(1, sp);
+    c->h_ser_t.clear();
+    c->h_ser_q.clear();
+    rc = push_scenarios(c);
+    if (rc != SWE_OK) return rc;
+    c->has_mesh = true;
+    c->has_state = false;
+    return SWE_OK;
+}
+
+int swe_set_bc_series(swe_ctx *c, int n, const double *t, const double *q)
+{
+    if (!c || n < 0 || (n > 0 && (!t || !q))) return set_err(c, SWE_ERR_ARG, "bad series");
+    if (!c->has_mesh) return set_err(c, SWE_ERR_STATE, "no mesh");
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(t[i + 1] > t[i])) return set_err(c, SWE_ERR_ARG, "series times must increase");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->h_ser_t.assign(t, t + n);
+    c->h_ser_q.assign(q, q + n);
+    c->h_scen[0].series_off = 0;
+    c->h_scen[0].series_n = n;
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    return push_scenarios(c);
+}
+
+int swe_set_state(swe_ctx *c, const void *h, const void *hu, const void *hv, int where, double t)
+{
+    if (!c || !h || !hu || !hv || (where != SWE_HOST && where != SWE_DEVICE))
+        return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (!c->has_mesh) return set_err(c, SWE_ERR_STATE, "no mesh uploaded");
+    HIP_OK(c, hipSetDevice(c->dev));
+    const size_t n = c->n_total, ts = c->tsize;
+    char *tmp = (char *)c->tmp3;
+    const hipMemcpyKind kind = where == SWE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_OK(c, hipMemcpyAsync(tmp, h, ts * n, kind, c->stream));
+    HIP_OK(c, hipMemcpyAsync(tmp + ts * n, hu, ts * n, kind, c->stream));
+    HIP_OK(c, hipMemcpyAsync(tmp + 2 * ts * n, hv, ts * n, kind, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    HIP_OK(c, hipMemsetAsync(c->health, 0, sizeof(int), c->stream));
+    const int B = 256, G = (int)((n + B - 1) / B);
+    if (ts == 8)
+        hipLaunchKernelGGL(k_pack_state<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const double *)tmp, (const double *)(tmp + 8 * n),
+                           (const double *)(tmp + 16 * n), (const double *)c->bed,
+                           (double4 *)c->U[0], c->flag, c->cfg.eps);
+    else
+        hipLaunchKernelGGL(k_pack_state<float>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const float *)tmp, (const float *)(tmp + 4 * n),
+                           (const float *)(tmp + 8 * n), (const float *)c->bed, (float4 *)c->U[0],
+                           c->flag, (float)c->cfg.eps);
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipMemcpyAsync(c->t0, &t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // slot 0: time and CFL minima of the initial state; slot 1 cleared
+    hipLaunchKernelGGL(k_clock_reset, dim3(1), dim3(64), 0, c->stream, c->clock, 1, 0, c->t0, 1);
+    hipLaunchKernelGGL(k_clock_reset, dim3(1), dim3(64), 0, c->stream, c->clock, 1, 1, c->t0, 0);
+    if (ts == 8)
+        hipLaunchKernelGGL(k_cfl_init<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const int4 *)c->nbr, (const double4 *)c->cell,
+                           (const double4 *)c->U[0], c->clock, 0, c->cfg.g, c->cfg.eps);
+    else
+        hipLaunchKernelGGL(k_cfl_init<float>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const int4 *)c->nbr, (const float4 *)c->cell, (const float4 *)c->U[0],
+                           c->clock, 0, (float)c->cfg.g, (float)c->cfg.eps);
+    HIP_OK(c, hipGetLastError());
+    int bad = 0;
+    HIP_OK(c, hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (bad) return set_err(c, SWE_ERR_STATE, "state has a negative or non-finite value");
+    c->step_count = 0;
+    c->has_state = true;
+    return SWE_OK;
+}
+
+int swe_read_state(swe_ctx *c, void *h, void *hu, void *hv, int where)
+{
+    if (!c || !h || !hu || !hv || (where != SWE_HOST && where != SWE_DEVICE))
+        return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    HIP_OK(c, hipSetDevice(c->dev));
+    const size_t n = c->n_total, ts = c->tsize;
+    char *tmp = (char *)c->tmp3;
+    const int B = 256, G = (int)((n + B - 1) / B);
+    void *Ucur = c->U[c->step_count & 1];
+    if (ts == 8)
+        hipLaunchKernelGGL(k_unpack_state<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const double4 *)Ucur, (double *)tmp, (double *)(tmp + 8 * n),
+                           (double *)(tmp + 16 * n));
+    else
+        hipLaunchKernelGGL(k_unpack_state<float>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const float4 *)Ucur, (float *)tmp, (float *)(tmp + 4 * n),
+                           (float *)(tmp + 8 * n));
+    HIP_OK(c, hipGetLastError());
+    const hipMemcpyKind kind = where == SWE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_OK(c, hipMemcpyAsync(h, tmp, ts * n, kind, c->stream));
+    HIP_OK(c, hipMemcpyAsync(hu, tmp + ts * n, ts * n, kind, c->stream));
+    HIP_OK(c, hipMemcpyAsync(hv, tmp + 2 * ts * n, ts * n, kind, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return health_status(c);
+}
+
+int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
+{
+    if (!c || n_steps < 0) return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    if (c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED)
+        return set_err(c, SWE_ERR_UNSUPPORTED, "learned limiter weights not set");
+    HIP_OK(c, hipSetDevice(c->dev));
+    if (!(dt_fixed > 0.0)) dt_fixed = 0.0;
+    HIP_OK(c, hipEventRecord(c->ev0, c->stream));
+    int done = 0;
+    while (done < n_steps) {
+        const bool aligned = (c->step_count % kGraphSteps) == 0;
+        if (c->use_graphs && aligned && n_steps - done >= kGraphSteps) {
+            if (!c->graph || c->graph_dt != dt_fixed) {
+                if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+                hipGraph_t gr = nullptr;
+                HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                int rc = SWE_OK;
+                for (int s = 0; s < kGraphSteps && rc == SWE_OK; ++s) rc = launch_step_any(c, s, dt_fixed);
+                hipError_t e = hipStreamEndCapture(c->stream, &gr);
+                if (rc != SWE_OK) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+                if (e != hipSuccess) return set_err(c, SWE_ERR_DEVICE, "graph capture failed");
+                e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) { c->graph = nullptr; return set_err(c, SWE_ERR_DEVICE, "graph instantiation failed"); }
+                c->graph_dt = dt_fixed;
+            }
+            HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
+            c->step_count += kGraphSteps;
+            done += kGraphSteps;
+        } else {
+            int rc = launch_step_any(c, c->step_count, dt_fixed);
+            if (rc != SWE_OK) return rc;
+            c->step_count += 1;
+            done += 1;
+        }
+    }
+    HIP_OK(c, hipEventRecord(c->ev1, c->stream));
+    c->ran = true;
+    return SWE_OK;
+}
+
+int swe_sync(swe_ctx *c)
+{
+    if (!c) return SWE_ERR_ARG;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return c->has_state ? health_status(c) : SWE_OK;
+}
+
+int swe_health(swe_ctx *c, int *bits)
+{
+    if (!c || !bits) return set_err(c, SWE_ERR_ARG, "null");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    HIP_OK(c, hipMemcpy(bits, c->health, sizeof(int), hipMemcpyDeviceToHost));
+    return SWE_OK;
+}
+
+int swe_time(swe_ctx *c, double *t)
+{
+    if (!c || !t) return set_err(c, SWE_ERR_ARG, "null");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    Clock k;
+    HIP_OK(c, hipMemcpy(&k, c->clock + (c->step_count % 3), sizeof(Clock), hipMemcpyDeviceToHost));
+    *t = k.t;
+    return health_status(c);
+}
+
+int swe_local_dt(swe_ctx *c, double *dt)
+{
+    if (!c || !dt) return set_err(c, SWE_ERR_ARG, "null");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    Clock k;
+    HIP_OK(c, hipMemcpy(&k, c->clock + (c->step_count % 3), sizeof(Clock), hipMemcpyDeviceToHost));
+    double v;
+    if (k.ratio_min == kInfBits) {
+        v = c->cfg.dt_max > 0 ? c->cfg.dt_max : 0.0;
+    } else {
+        double r, rad, lam;
+        std::memcpy(&r, &k.ratio_min, 8);
+        std::memcpy(&rad, &k.rad_min, 8);
+        std::memcpy(&lam, &k.lam_max, 8);
+        v = c->cfg.cfl_rule == 1 ? c->cfg.cfl * rad / lam : c->cfg.cfl * r;
+        if (c->cfg.dt_max > 0 && v > c->cfg.dt_max) v = c->cfg.dt_max;
+    }
+    *dt = v;
+    return SWE_OK;
+}
+
+int swe_ghost_sizes(const swe_ctx *c, int32_t *n_send, int32_t *n_ghost)
+{
+    if (!c || !n_send || !n_ghost) return SWE_ERR_ARG;
+    *n_send = c->n_send;
+    *n_ghost = c->n_ghost;
+    return SWE_OK;
+}
+
+int swe_pack_ghosts(swe_ctx *c, void *buf)
+{
+    if (!c || (!buf && c->n_send > 0)) return set_err(c, SWE_ERR_ARG, "null buffer");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    if (c->n_send == 0) return SWE_OK;
+    HIP_OK(c, hipSetDevice(c->dev));
+    const int B = 256, G = (c->n_send + B - 1) / B;
+    void *Ucur = c->U[c->step_count & 1];
+    if (c->tsize == 8)
+        hipLaunchKernelGGL(k_pack_ghosts<double>, dim3(G), dim3(B), 0, c->stream, c->n_send,
+                           c->send_idx, (const double4 *)Ucur, (double *)buf);
+    else
+        hipLaunchKernelGGL(k_pack_ghosts<float>, dim3(G), dim3(B), 0, c->stream, c->n_send,
+                           c->send_idx, (const float4 *)Ucur, (float *)buf);
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return SWE_OK;
+}
+
+int swe_unpack_ghosts(swe_ctx *c, const void *buf)
+{
+    if (!c || (!buf && c->n_ghost > 0)) return set_err(c, SWE_ERR_ARG, "null buffer");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    if (c->n_ghost == 0) return SWE_OK;
+    HIP_OK(c, hipSetDevice(c->dev));
+    const int B = 256, G = (c->n_ghost + B - 1) / B;
+    void *Ucur = c->U[c->step_count & 1];
+    if (c->tsize == 8)
+        hipLaunchKernelGGL(k_unpack_ghosts<double>, dim3(G), dim3(B), 0, c->stream, c->n_owned,
+                           c->n_ghost, (const double *)buf, (double4 *)Ucur);
+    else
+        hipLaunchKernelGGL(k_unpack_ghosts<float>, dim3(G), dim3(B), 0, c->stream, c->n_owned,
+                           c->n_ghost, (const float *)buf, (float4 *)Ucur);
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return SWE_OK;
+}
+
+int swe_last_step_ms(swe_ctx *c, float *ms)
+{
+    if (!c || !ms) return SWE_ERR_ARG;
+    if (!c->ran) return set_err(c, SWE_ERR_STATE, "no step yet");
+    HIP_OK(c, hipEventSynchronize(c->ev1));
+    HIP_OK(c, hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return SWE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+// Device-side numerics of the shallow-water step (Delmas & Soulaimani,
+// Sec. 6.1 - 6.2): interface reconstruction, hydrostatic reconstruction,
+// HLLC / WAF fluxes and boundary fluxes, written once for float and double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace swe {
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+enum { kHLLC1 = 0, kMUSCL = 1, kWAF = 2 };
+enum { kMinmod = 0, kSuperbee = 1, kVanAlbada = 2, kLearned = 3, kZeroSlope = 4 };
+enum { kWafSuperbee = 0, kWafGodunov = 1, kWafUnlimited = 2 };
+enum { kBcWall = -1, kBcTransmissive = -2, kBcInflow = -3, kBcOutflow = -4, kBcHalo = -5 };
+enum { kHealthNonfinite = 1, kHealthNegDepth = 2, kHealthClipped = 4 };
+
+// Per-scenario step clock, three slots per scenario rotating with the step
+// index: the current step reads slot s, reduces the next CFL step into slot
+// s+1 and clears slot s+2.  CFL minima are kept as the bit patterns of
+// non-negative doubles, whose integer order is their numeric order.
+struct Clock {
+    double t;
+    unsigned long long ratio_min;  // min over wet owned cells of R_i / lambda_i
+    unsigned long long rad_min;    // min R_i over wet owned cells
+    unsigned long long lam_max;    // max lambda_i over wet owned cells
+};
+
+struct ScenParams {
+    double inflow_q;         // constant total discharge
+    double inv_inflow_len;   // 1 / total inflow edge length
+    double outflow_stage;
+    int series_off, series_n;  // hydrograph points in the series arrays
+};
+
+template <typename T> struct Half { T h, b, un, ut; };
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+
+// velocity of a cell state in the frame (n, t = rot90(n))
+template <typename T, typename T4>
+__device__ __forceinline__ void frame_vel(const T4 &U, T nx, T ny, T eps, T &un, T &ut)
+{
+    const T u = U.x > eps ? U.y / U.x : T(0);
+    const T v = U.x > eps ? U.z / U.x : T(0);
+    un = u * nx + v * ny;
+    ut = -u * ny + v * nx;
+}
+
+// Slope limiters of Sec. 6.2.3: beta form branching on the sign of the jump
+// across the edge (beta = 1 MINBEE, beta = 2 SUPERBEE), and van Albada.
+template <typename T, int LIM>
+__device__ __forceinline__ T limit(T sb, T sf)
+{
+    if (LIM == kVanAlbada) return sb * sf > T(0) ? sb * sf * (sb + sf) / (sb * sb + sf * sf) : T(0);
+    if (LIM == kZeroSlope) return T(0);
+    const T beta = LIM == kSuperbee ? T(2) : T(1);
+    if (sf > T(0)) return tmax(T(0), tmax(tmin(beta * sb, sf), tmin(sb, beta * sf)));
+    if (sf < T(0)) return tmin(T(0), tmin(tmax(beta * sb, sf), tmax(sb, beta * sf)));
+    return T(0);
+}
+
+// Interface values of cell c across one of its edges, in c's outward-normal
+// frame (Sec. 6.2.3 on the rotated states T_n U): h, b- and the normal and
+// tangential velocities.  Uk is the cell across the edge, Ua / Ub the two
+// other neighbours of c (upwind cells).  dist = (1/d_up, 1/d_fwd,
+// 1/d_central, d_fwd).  First order unless the scheme is MUSCL, all stencil
+// cells are wet, at least one upwind cell exists and h- >= 0.
+template <typename T, typename T4, int SCHEME, int LIM>
+__device__ __forceinline__ Half<T> reconstruct(const T4 &Uc, const T4 &Uk, const T4 &Ua, bool ha,
+                                               const T4 &Ub, bool hb, T nx, T ny, T dm,
+                                               const T4 &dist, float phi, T eps)
+{
+    Half<T> r;
+    r.h = Uc.x;
+    r.b = Uc.w;
+    frame_vel(Uc, nx, ny, eps, r.un, r.ut);
+    if (SCHEME != kMUSCL) return r;
+    if (!(Uc.x > eps) || !(Uk.x > eps)) return r;
+    if ((ha && !(Ua.x > eps)) || (hb && !(Ub.x > eps)) || (!ha && !hb)) return r;
+    T qc[4] = {Uc.x, Uc.x + Uc.w, r.un, r.ut};
+    T qk[4];
+    qk[0] = Uk.x;
+    qk[1] = Uk.x + Uk.w;
+    frame_vel(Uk, nx, ny, eps, qk[2], qk[3]);
+    T qu[4];
+    if (ha && hb) {
+        T qa[4], qb[4];
+        qa[0] = Ua.x; qa[1] = Ua.x + Ua.w; frame_vel(Ua, nx, ny, eps, qa[2], qa[3]);
+        qb[0] = Ub.x; qb[1] = Ub.x + Ub.w; frame_vel(Ub, nx, ny, eps, qb[2], qb[3]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qu[i] = T(0.5) * (qa[i] + qb[i]);
+    } else {
+        const T4 &Uo = ha ? Ua : Ub;
+        qu[0] = Uo.x; qu[1] = Uo.x + Uo.w; frame_vel(Uo, nx, ny, eps, qu[2], qu[3]);
+    }
+    T out[4];
+    bool done = false;
+    if (LIM == kLearned) {
+        if (phi >= 0.0f && phi <= 1.0f) {  // a NaN fails both tests
+            const T p = T(phi);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[i] = qc[i] + dm * (p * ((qk[i] - qu[i]) * dist.z));
+            done = out[0] >= T(0);
+        }
+    }
+    if (!done) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T sb = (qc[i] - qu[i]) * dist.x, sf = (qk[i] - qc[i]) * dist.y;
+            out[i] = qc[i] + dm * limit<T, (LIM == kLearned ? kMinmod : LIM)>(sb, sf);
+        }
+    }
+    if (out[0] < T(0)) return r;
+    r.h = out[0];
+    r.b = out[1] - out[0];
+    r.un = out[2];
+    r.ut = out[3];
+    return r;
+}
+
+// HLL wave fan (Sec. 6.2.1): speeds, physical fluxes and star flux; states
+// in the normal frame (h, q_n, q_t).  Dry sides use the dry-bed speeds.
+template <typename T> struct Fan {
+    T hL, hR, uL, uR, vL, vR, qL, qR;
+    T GL[3], GR[3], Fs[2];
+    T SL, SR, Ss;
+    bool dry;
+};
+
+template <typename T>
+__device__ __forceinline__ void wave_fan(T g, T eps, const T UL[3], const T UR[3], Fan<T> &W)
+{
+    W.hL = UL[0]; W.hR = UR[0];
+    W.dry = (W.hL <= eps && W.hR <= eps);
+    const bool wl = W.hL > eps, wr = W.hR > eps;
+    W.uL = wl ? UL[1] / W.hL : T(0); W.vL = wl ? UL[2] / W.hL : T(0);
+    W.uR = wr ? UR[1] / W.hR : T(0); W.vR = wr ? UR[2] / W.hR : T(0);
+    W.qL = wl ? UL[1] : T(0); W.qR = wr ? UR[1] : T(0);
+    if (W.dry) return;
+    const T hL = W.hL, hR = W.hR, uL = W.uL, uR = W.uR;
+    const T aL = sqrt(g * hL), aR = sqrt(g * hR);
+    if (!wr) {
+        W.SL = uL - aL; W.SR = uL + T(2) * aL; W.Ss = W.SR;
+    } else if (!wl) {
+        W.SL = uR - T(2) * aR; W.SR = uR + aR; W.Ss = W.SL;
+    } else {
+        const T h0 = T(0.5) * (hL + hR) - T(0.25) * (uR - uL) * (hL + hR) / (aR + aL);
+        T hs;
+        if (h0 <= tmin(hL, hR)) {
+            const T t = T(0.5) * (aR + aL) + T(0.25) * (uL - uR);
+            hs = t > T(0) ? t * t / g : T(0);
+        } else {
+            const T gL = sqrt(g * (h0 + hL) / (T(2) * h0 * hL));
+            const T gR = sqrt(g * (h0 + hR) / (T(2) * h0 * hR));
+            hs = (hL * gL + hR * gR + uL - uR) / (gL + gR);
+        }
+        const T pL = hs > hL ? sqrt((hs + hL) * hs / (T(2) * hL * hL)) : T(1);
+        const T pR = hs > hR ? sqrt((hs + hR) * hs / (T(2) * hR * hR)) : T(1);
+        W.SL = uL - aL * pL;
+        W.SR = uR + aR * pR;
+        W.Ss = (W.SL * hR * (uR - W.SR) - W.SR * hL * (uL - W.SL)) /
+               (hR * (uR - W.SR) - hL * (uL - W.SL));
+    }
+    W.GL[0] = W.qL; W.GL[1] = W.qL * uL + T(0.5) * g * hL * hL; W.GL[2] = W.qL * W.vL;
+    W.GR[0] = W.qR; W.GR[1] = W.qR * uR + T(0.5) * g * hR * hR; W.GR[2] = W.qR * W.vR;
+    const T d = W.SR - W.SL;
+    W.Fs[0] = (W.SR * W.GL[0] - W.SL * W.GR[0] + W.SR * W.SL * (hR - hL)) / d;
+    W.Fs[1] = (W.SR * W.GL[1] - W.SL * W.GR[1] + W.SR * W.SL * (W.qR - W.qL)) / d;
+}
+
+template <typename T>
+__device__ __forceinline__ void flux_hllc(T g, T eps, const T UL[3], const T UR[3], T F[3])
+{
+    Fan<T> W;
+    wave_fan(g, eps, UL, UR, W);
+    if (W.dry) { F[0] = F[1] = F[2] = T(0); return; }
+    if (W.SL >= T(0)) { F[0] = W.GL[0]; F[1] = W.GL[1]; F[2] = W.GL[2]; return; }
+    if (W.SR <= T(0)) { F[0] = W.GR[0]; F[1] = W.GR[1]; F[2] = W.GR[2]; return; }
+    F[0] = W.Fs[0];
+    F[1] = W.Fs[1];
+    F[2] = F[0] * (W.Ss >= T(0) ? W.vL : W.vR);  // contact: upwind tangential velocity
+}
+
+// WAF (Sec. 6.2.2) with the superbee A(r, c) of eq. (eq:superbee).
+template <typename T> __device__ __forceinline__ T superbee_A(T r, T c)
+{
+    const T ac = c < T(0) ? -c : c;
+    if (r <= T(0)) return T(1);
+    if (r <= T(0.5)) return T(1) - T(2) * (T(1) - ac) * r;
+    if (r <= T(1)) return ac;
+    if (r <= T(2)) return T(1) - (T(1) - ac) * r;
+    return T(2) * ac - T(1);
+}
+
+template <typename T> __device__ __forceinline__ T sgn(T x)
+{
+    return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
+}
+
+struct WafRatio { bool hasLu, hasRu; };
+
+template <typename T>
+__device__ __forceinline__ T waf_ratio(T S, T qL, T qR, T qLu, T qRu, bool hasLu, bool hasRu)
+{
+    const T dloc = qR - qL;
+    if (dloc == T(0)) return T(0);
+    if (S >= T(0)) return hasLu ? (qL - qLu) / dloc : T(0);
+    return hasRu ? (qRu - qR) / dloc : T(0);
+}
+
+template <typename T, int MODE> __device__ __forceinline__ T waf_A(T r, T c)
+{
+    if (MODE == kWafGodunov) return T(1);
+    if (MODE == kWafUnlimited) return c < T(0) ? -c : c;
+    return superbee_A(r, c);
+}
+
+// eta and v of L, R and of their upwind means; has*u: an upwind value exists
+template <typename T> struct WafIn {
+    T eL, eR, eLu, eRu, vL, vR, vLu, vRu;
+    bool hasLu, hasRu;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], const T UR[3],
+                                         const WafIn<T> &w, T F[3])
+{
+    Fan<T> W;
+    wave_fan(g, eps, UL, UR, W);
+    if (W.dry) { F[0] = F[1] = F[2] = T(0); return; }
+    const T cL = W.SL * dt_dx, cR = W.SR * dt_dx, cs = W.Ss * dt_dx;
+    const T AL = waf_A<T, MODE>(waf_ratio(W.SL, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cL);
+    const T AR = waf_A<T, MODE>(waf_ratio(W.SR, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cR);
+    const T As = waf_A<T, MODE>(waf_ratio(W.Ss, w.vL, w.vR, w.vLu, w.vRu, w.hasLu, w.hasRu), cs);
+    const T wL = T(0.5) * (T(1) + sgn(cL) * AL);
+    const T wLR = T(0.5) * (sgn(cR) * AR - sgn(cL) * AL);
+    const T wR = T(0.5) * (T(1) - sgn(cR) * AR);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) F[i] = wL * W.GL[i] + wLR * W.Fs[i] + wR * W.GR[i];
+    const T wLs = T(0.5) * (T(1) + sgn(cs) * As), wRs = T(0.5) * (T(1) - sgn(cs) * As);
+    F[2] = (wLs * W.vL + wRs * W.vR) * F[0];
+}
+
+}  // namespace swe

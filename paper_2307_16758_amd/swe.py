@@ -1,0 +1,378 @@
+"""Thin ctypes binding of libswe.so (include/swe.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels (device) or its C++ mesh toolkit (host).  Host arrays are numpy
+arrays; device buffers are torch CUDA tensors (``data_ptr()``), used as
+plumbing for memory only.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe.so")
+
+SWE_ABI_VERSION = 1
+SWE_OK = 0
+ERRORS = {-1: "SWE_ERR_ARG", -2: "SWE_ERR_MESH", -3: "SWE_ERR_STATE", -4: "SWE_ERR_NONFINITE",
+          -5: "SWE_ERR_NEGATIVE_DEPTH", -6: "SWE_ERR_DEVICE", -7: "SWE_ERR_OOM",
+          -8: "SWE_ERR_UNSUPPORTED"}
+F32, F64 = 0, 1
+HLLC1, MUSCL, WAF = 0, 1, 2
+EULER, RK2 = 0, 1
+MINMOD, SUPERBEE, VANALBADA, LEARNED, ZEROSLOPE = 0, 1, 2, 3, 4
+WAF_SUPERBEE, WAF_GODUNOV, WAF_UNLIMITED = 0, 1, 2
+HOST, DEVICE = 0, 1
+BC_WALL, BC_TRANSMISSIVE, BC_INFLOW, BC_OUTFLOW, BC_HALO = -1, -2, -3, -4, -5
+HEALTH_NONFINITE, HEALTH_NEGDEPTH, HEALTH_CLIPPED = 1, 2, 4
+
+
+class SweError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libswe.so not built ({LIB_PATH}); run python paper_2307_16758_amd/build.py")
+_lib = C.CDLL(LIB_PATH)
+
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+
+
+class swe_config(C.Structure):
+    _fields_ = [("abi_version", C.c_int), ("precision", C.c_int), ("scheme", C.c_int),
+                ("integrator", C.c_int), ("limiter", C.c_int), ("waf_limiter", C.c_int),
+                ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
+                ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
+                ("block", C.c_int), ("reserved", C.c_int * 7)]
+
+
+class swe_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("node_xy", f64p), ("n_owned", C.c_int32),
+                ("n_total", C.c_int32), ("cell_nodes", i32p), ("cell_gid", C.POINTER(C.c_int64)),
+                ("cell_nbr", i32p), ("cell_b", f64p), ("cell_manning", f64p),
+                ("n_peers", C.c_int32), ("peer_part", i32p), ("recv_off", i32p),
+                ("send_off", i32p), ("send_idx", i32p), ("inflow_q", C.c_double),
+                ("inflow_length", C.c_double), ("outflow_stage", C.c_double)]
+
+
+class swe_subdomain_view(C.Structure):
+    _fields_ = [("n_owned", C.c_int32), ("n_total", C.c_int32), ("n_peers", C.c_int32),
+                ("n_send", C.c_int32)] + [
+        (n, i32p) for n in ("l2g", "layer", "owner", "nbr", "peers", "recv_off", "send_off",
+                            "send_idx")]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("swe_config_default", None, [C.POINTER(swe_config)])
+_sig("swe_create", C.c_int, [C.POINTER(swe_config), C.POINTER(C.c_void_p)])
+_sig("swe_destroy", None, [C.c_void_p])
+_sig("swe_last_error", C.c_char_p, [C.c_void_p])
+_sig("swe_strerror", C.c_char_p, [C.c_int])
+_sig("swe_mesh_upload", C.c_int, [C.c_void_p, C.POINTER(swe_mesh)])
+_sig("swe_set_bc_series", C.c_int, [C.c_void_p, C.c_int, f64p, f64p])
+_sig("swe_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                C.c_double])
+_sig("swe_read_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int])
+_sig("swe_step", C.c_int, [C.c_void_p, C.c_int, C.c_double])
+_sig("swe_sync", C.c_int, [C.c_void_p])
+_sig("swe_time", C.c_int, [C.c_void_p, f64p])
+_sig("swe_local_dt", C.c_int, [C.c_void_p, f64p])
+_sig("swe_health", C.c_int, [C.c_void_p, C.POINTER(C.c_int)])
+_sig("swe_pack_ghosts", C.c_int, [C.c_void_p, C.c_void_p])
+_sig("swe_unpack_ghosts", C.c_int, [C.c_void_p, C.c_void_p])
+_sig("swe_ghost_sizes", C.c_int, [C.c_void_p, i32p, i32p])
+_sig("swe_last_step_ms", C.c_int, [C.c_void_p, C.POINTER(C.c_float)])
+_sig("swe_dual_graph", C.c_int, [C.c_int32, C.c_int32, i32p, i32p])
+_sig("swe_partition_bfs", C.c_int, [C.c_int32, i32p, C.c_int32, i32p])
+_sig("swe_edge_length_sum", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, C.POINTER(C.c_int8),
+                                      C.c_int32, f64p])
+_sig("swe_morton_keys", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, C.POINTER(C.c_uint32)])
+_sig("swe_subdomain_build", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, i32p,
+                                      C.POINTER(C.c_int8), i32p, C.c_int32, C.c_int32,
+                                      C.c_int32, C.POINTER(C.c_void_p)])
+_sig("swe_subdomain_view_get", C.c_int, [C.c_void_p, C.POINTER(swe_subdomain_view)])
+_sig("swe_subdomain_free", None, [C.c_void_p])
+
+EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error", "swe_strerror",
+            "swe_mesh_upload", "swe_set_bc_series", "swe_set_state", "swe_read_state",
+            "swe_step", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
+            "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
+            "swe_dual_graph", "swe_partition_bfs", "swe_edge_length_sum", "swe_morton_keys", "swe_subdomain_build",
+            "swe_subdomain_view_get", "swe_subdomain_free"]
+
+
+def lib():
+    return _lib
+
+
+def _i32(a):
+    return a.ctypes.data_as(i32p)
+
+
+def _f64(a):
+    return a.ctypes.data_as(f64p)
+
+
+def _check(rc, ctx=None):
+    if rc != SWE_OK:
+        msg = _lib.swe_last_error(ctx).decode() if ctx else _lib.swe_strerror(rc).decode()
+        raise SweError(rc, msg)
+
+
+# ------------------------------------------------------------ host toolkit
+def swe_dual_graph(n_nodes: int, cell_nodes: np.ndarray) -> np.ndarray:
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    nbr = np.empty(t.shape, np.int32)
+    _check(_lib.swe_dual_graph(n_nodes, t.shape[0], _i32(t), _i32(nbr)))
+    return nbr
+
+
+def swe_partition_bfs(nbr: np.ndarray, P: int) -> np.ndarray:
+    nb = np.ascontiguousarray(nbr, np.int32)
+    part = np.empty(nb.shape[0], np.int32)
+    _check(_lib.swe_partition_bfs(nb.shape[0], _i32(nb), P, _i32(part)))
+    return part
+
+
+def swe_edge_length_sum(node_xy, cell_nodes, bc, tag) -> float:
+    x = np.ascontiguousarray(node_xy, np.float64)
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    b = np.ascontiguousarray(bc, np.int8)
+    out = C.c_double()
+    _check(_lib.swe_edge_length_sum(x.shape[0], _f64(x), t.shape[0], _i32(t),
+                                    b.ctypes.data_as(C.POINTER(C.c_int8)), tag, C.byref(out)))
+    return out.value
+
+
+def swe_morton_keys(node_xy: np.ndarray, cell_nodes: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(node_xy, np.float64)
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    key = np.empty(t.shape[0], np.uint32)
+    _check(_lib.swe_morton_keys(x.shape[0], _f64(x), t.shape[0], _i32(t),
+                                key.ctypes.data_as(C.POINTER(C.c_uint32))))
+    return key
+
+
+@dataclass
+class SubDomain:
+    n_owned: int
+    n_total: int
+    l2g: np.ndarray
+    layer: np.ndarray
+    owner: np.ndarray
+    nbr: np.ndarray
+    peers: np.ndarray
+    recv_off: np.ndarray
+    send_off: np.ndarray
+    send_idx: np.ndarray
+
+
+def swe_subdomain_build(node_xy, cell_nodes, nbr, bc, part, P, p, k) -> SubDomain:
+    x = np.ascontiguousarray(node_xy, np.float64)
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    nb = np.ascontiguousarray(nbr, np.int32)
+    b = np.ascontiguousarray(bc, np.int8)
+    pa = np.ascontiguousarray(part, np.int32)
+    h = C.c_void_p()
+    _check(_lib.swe_subdomain_build(x.shape[0], _f64(x), t.shape[0], _i32(t), _i32(nb),
+                                    b.ctypes.data_as(C.POINTER(C.c_int8)), _i32(pa), P, p, k,
+                                    C.byref(h)))
+    v = swe_subdomain_view()
+    _check(_lib.swe_subdomain_view_get(h, C.byref(v)))
+
+    def arr(ptr, n):
+        return np.ctypeslib.as_array(ptr, shape=(n,)).copy() if n > 0 else np.zeros(0, np.int32)
+
+    sd = SubDomain(v.n_owned, v.n_total, arr(v.l2g, v.n_total), arr(v.layer, v.n_total),
+                   arr(v.owner, v.n_total), arr(v.nbr, 3 * v.n_total).reshape(-1, 3),
+                   arr(v.peers, v.n_peers), arr(v.recv_off, v.n_peers + 1),
+                   arr(v.send_off, v.n_peers + 1), arr(v.send_idx, v.n_send))
+    _lib.swe_subdomain_free(h)
+    return sd
+
+
+# --------------------------------------------------------------- the mesh
+@dataclass
+class MeshArrays:
+    """Arrays of a swe_mesh (host side), kept alive while uploaded."""
+    node_xy: np.ndarray
+    n_owned: int
+    cell_nodes: np.ndarray
+    cell_gid: np.ndarray
+    cell_nbr: np.ndarray
+    cell_b: np.ndarray
+    cell_manning: np.ndarray
+    peers: np.ndarray
+    recv_off: np.ndarray
+    send_off: np.ndarray
+    send_idx: np.ndarray
+    inflow_q: float = 0.0
+    inflow_length: float = 0.0
+    outflow_stage: float = 0.0
+
+    @property
+    def n_total(self):
+        return int(self.cell_nodes.shape[0])
+
+    def c_struct(self) -> swe_mesh:
+        for name in ("node_xy", "cell_b", "cell_manning"):
+            setattr(self, name, np.ascontiguousarray(getattr(self, name), np.float64))
+        for name in ("cell_nodes", "cell_nbr", "peers", "recv_off", "send_off", "send_idx"):
+            setattr(self, name, np.ascontiguousarray(getattr(self, name), np.int32))
+        self.cell_gid = np.ascontiguousarray(self.cell_gid, np.int64)
+        m = swe_mesh()
+        m.n_nodes = self.node_xy.shape[0]
+        m.node_xy = _f64(self.node_xy)
+        m.n_owned = self.n_owned
+        m.n_total = self.n_total
+        m.cell_nodes = _i32(self.cell_nodes)
+        m.cell_gid = self.cell_gid.ctypes.data_as(C.POINTER(C.c_int64))
+        m.cell_nbr = _i32(self.cell_nbr)
+        m.cell_b = _f64(self.cell_b)
+        m.cell_manning = _f64(self.cell_manning)
+        m.n_peers = self.peers.shape[0]
+        m.peer_part = _i32(self.peers)
+        m.recv_off = _i32(self.recv_off)
+        m.send_off = _i32(self.send_off)
+        m.send_idx = _i32(self.send_idx)
+        m.inflow_q = self.inflow_q
+        m.inflow_length = self.inflow_length
+        m.outflow_stage = self.outflow_stage
+        return m
+
+
+def mesh_from_subdomain(node_xy, cell_nodes, cell_b, cell_manning, sd: SubDomain,
+                        inflow_q=0.0, inflow_length=0.0, outflow_stage=0.0) -> MeshArrays:
+    l2g = sd.l2g
+    return MeshArrays(node_xy=node_xy, n_owned=sd.n_owned, cell_nodes=cell_nodes[l2g],
+                      cell_gid=l2g.astype(np.int64), cell_nbr=sd.nbr,
+                      cell_b=np.asarray(cell_b)[l2g], cell_manning=np.asarray(cell_manning)[l2g],
+                      peers=sd.peers, recv_off=sd.recv_off, send_off=sd.send_off,
+                      send_idx=sd.send_idx, inflow_q=inflow_q, inflow_length=inflow_length,
+                      outflow_stage=outflow_stage)
+
+
+# ----------------------------------------------------------- the solver
+def config(**kw) -> swe_config:
+    cfg = swe_config()
+    _lib.swe_config_default(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def _ptr(a, where):
+    if where == DEVICE:
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(a.ctypes.data)
+
+
+class Solver:
+    """One swe_ctx: a sub-domain (or a whole mesh) on one GPU."""
+
+    def __init__(self, **cfg_kw):
+        self.cfg = config(**cfg_kw)
+        self.dtype = np.float64 if self.cfg.precision == F64 else np.float32
+        h = C.c_void_p()
+        _check(_lib.swe_create(C.byref(self.cfg), C.byref(h)))
+        self.ctx = h
+        self.mesh = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.swe_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, rc):
+        _check(rc, self.ctx)
+
+    def mesh_upload(self, mesh: MeshArrays):
+        s = mesh.c_struct()
+        self._chk(_lib.swe_mesh_upload(self.ctx, C.byref(s)))
+        self.mesh = mesh
+
+    def set_bc_series(self, t, q):
+        t = np.ascontiguousarray(t, np.float64)
+        q = np.ascontiguousarray(q, np.float64)
+        self._chk(_lib.swe_set_bc_series(self.ctx, t.shape[0], _f64(t), _f64(q)))
+
+    def set_state(self, h, hu, hv, t=0.0):
+        if hasattr(h, "data_ptr"):
+            where = DEVICE
+        else:
+            where = HOST
+            h, hu, hv = (np.ascontiguousarray(a, self.dtype) for a in (h, hu, hv))
+        self._chk(_lib.swe_set_state(self.ctx, _ptr(h, where), _ptr(hu, where), _ptr(hv, where),
+                                     where, float(t)))
+
+    def read_state(self, out=None):
+        if out is None:
+            n = self.mesh.n_total
+            out = tuple(np.empty(n, self.dtype) for _ in range(3))
+            where = HOST
+        else:
+            where = DEVICE if hasattr(out[0], "data_ptr") else HOST
+        self._chk(_lib.swe_read_state(self.ctx, *(_ptr(a, where) for a in out), where))
+        return out
+
+    def step(self, n_steps, dt_fixed=0.0):
+        self._chk(_lib.swe_step(self.ctx, int(n_steps), float(dt_fixed)))
+
+    def sync(self):
+        self._chk(_lib.swe_sync(self.ctx))
+
+    def time(self):
+        t = C.c_double()
+        self._chk(_lib.swe_time(self.ctx, C.byref(t)))
+        return t.value
+
+    def local_dt(self):
+        t = C.c_double()
+        self._chk(_lib.swe_local_dt(self.ctx, C.byref(t)))
+        return t.value
+
+    def health(self):
+        b = C.c_int()
+        self._chk(_lib.swe_health(self.ctx, C.byref(b)))
+        return b.value
+
+    def ghost_sizes(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._chk(_lib.swe_ghost_sizes(self.ctx, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def pack_ghosts(self, buf):
+        self._chk(_lib.swe_pack_ghosts(self.ctx, C.c_void_p(buf.data_ptr())))
+
+    def unpack_ghosts(self, buf):
+        self._chk(_lib.swe_unpack_ghosts(self.ctx, C.c_void_p(buf.data_ptr())))
+
+    def last_step_ms(self):
+        f = C.c_float()
+        self._chk(_lib.swe_last_step_ms(self.ctx, C.byref(f)))
+        return f.value

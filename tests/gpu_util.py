@@ -1,0 +1,59 @@
+"""Shared set-up of the GPU tests: the same problem, numbered the same way,
+on the HIP library (through the C ABI) and on the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+
+def lib():
+    from paper_2307_16758_amd import swe
+    from paper_2307_16758_amd.problem import prepare_scenario
+    return swe, prepare_scenario
+
+
+SCHEME_KW = {
+    "hllc1": dict(scheme=0, integrator=0, limiter=0),
+    "muscl_minmod_rk2": dict(scheme=1, integrator=1, limiter=0),
+    "muscl_superbee_rk2": dict(scheme=1, integrator=1, limiter=1),
+    "muscl_vanalbada_rk2": dict(scheme=1, integrator=1, limiter=2),
+    "muscl_minmod_euler": dict(scheme=1, integrator=0, limiter=0),
+    "waf": dict(scheme=2, integrator=0, limiter=0),
+}
+
+
+def make_pair(sc, name, precision, P=1, p=0, k=0, prepared=None, **cfg):
+    """(solver, oracle mesh, oracle params, prepared) for one scenario."""
+    swe, prepare_scenario = lib()
+    pr = prepared if prepared is not None else prepare_scenario(sc, P=P, p=p, k=k)
+    kw = dict(SCHEME_KW[name])
+    kw.update(cfg)
+    s = swe.Solver(precision=precision, **kw)
+    s.mesh_upload(pr.mesh)
+    if sc.hydrograph is not None:
+        s.set_bc_series(*sc.hydrograph)
+    l2g = pr.sub.l2g
+    s.set_state(sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    M = O.Mesh(sc.mesh.xy, sc.mesh.tri[l2g], pr.sub.nbr, sc.b[l2g], sc.manning[l2g],
+               gid=l2g, n_owned=pr.sub.n_owned)
+    okw = {k_: v for k_, v in kw.items() if k_ in ("scheme", "integrator", "limiter")}
+    for k_ in ("waf_limiter", "cfl_rule", "cfl", "dt_max", "eps"):
+        if k_ in cfg:
+            okw[k_] = cfg[k_]
+    par = O.scenario_params(sc, **okw)
+    par.inflow_len = pr.mesh.inflow_length if pr.mesh.inflow_length > 0 else 1.0
+    return s, M, par, pr
+
+
+def rel_err(a, r, n_owned=None):
+    """Per field: max |a - r| / max |r| over owned cells (0/0 -> 0)."""
+    if n_owned is not None:
+        a, r = a[:n_owned], r[:n_owned]
+    d = np.abs(np.asarray(a, np.float64) - r).max() if r.size else 0.0
+    s = np.abs(r).max() if r.size else 0.0
+    return d / s if s > 0 else d
+
+
+def state_errors(gpu_state, ref_state, n_owned):
+    return tuple(rel_err(g, r, n_owned) for g, r in zip(gpu_state, ref_state))

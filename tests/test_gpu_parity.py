@@ -1,0 +1,170 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances, per field, as max |gpu - oracle| / max |oracle| over owned cells:
+* FP64 kernels: 1e-12 for first-order HLLC (config 1, 200 steps) and 1e-10
+  for the second-order schemes (round-off of a different but equally exact
+  operation order, grown over the run);
+* FP32 kernels: 1e-4 after 1000 MUSCL-HLLC-RK2 steps (the required bound),
+  in fixed-dt mode so that both sides integrate the same time levels.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import make_pair, rel_err, state_errors, lib
+from swe_inputs import config1, river_channel, lake_at_rest, dam_break_channel, strip_riemann
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(s, M, par, sc, l2g, nsteps, dt_fixed=0.0):
+    s.step(nsteps, dt_fixed)
+    g = s.read_state()
+    r = M.run(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g], nsteps, dt_fixed=dt_fixed)
+    return g, r
+
+
+def test_config1_hllc_fp64_cfl_mode():
+    """Config 1: 16,000-cell dam break, first-order HLLC, FP64, 200 CFL steps."""
+    sc = config1()
+    s, M, par, pr = make_pair(sc, "hllc1", precision=1)
+    g, r = _run_both(s, M, par, sc, pr.sub.l2g, 200)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    assert max(errs) <= 1e-12, errs
+    assert s.time() == pytest.approx(r[3], rel=1e-12)
+    assert s.health() == 0
+
+
+def test_config1_hllc_fp32():
+    sc = config1()
+    s, M, par, pr = make_pair(sc, "hllc1", precision=0)
+    dt = M.dt(par, sc.h, sc.hu, sc.hv)
+    g, r = _run_both(s, M, par, sc, pr.sub.l2g, 200, dt_fixed=dt)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    assert max(errs) <= 1e-4, errs
+
+
+def small_river(seed=2):
+    return river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=seed)
+
+
+@pytest.mark.parametrize("name", ["muscl_minmod_rk2", "muscl_superbee_rk2", "muscl_vanalbada_rk2"])
+def test_river_muscl_fp64(name):
+    sc = small_river()
+    s, M, par, pr = make_pair(sc, name, precision=1)
+    l2g = pr.sub.l2g
+    dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    g, r = _run_both(s, M, par, sc, l2g, 300, dt_fixed=dt)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    assert max(errs) <= 1e-10, errs
+
+
+def test_river_muscl_fp32_1000_steps():
+    """Config-2 recipe at 10,240 cells (inflow, fixed-stage outflow, Manning,
+    dry banks, bumps): FP32 MUSCL-HLLC-RK2 within 1e-4 of the FP64 oracle
+    after 1000 steps."""
+    sc = small_river()
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=0)
+    l2g = pr.sub.l2g
+    dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    g, r = _run_both(s, M, par, sc, l2g, 1000, dt_fixed=dt)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    print("fp32 muscl 1000 steps rel errs", errs)
+    assert max(errs) <= 1e-4, errs
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-10), (0, 1e-3)])
+def test_dam_break_waf(prec, tol):
+    sc = dam_break_channel(Lx=50.0, Ly=10.0, nx=100, ny=20, x_dam=25.0)
+    s, M, par, pr = make_pair(sc, "waf", precision=prec)
+    l2g = pr.sub.l2g
+    dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    g, r = _run_both(s, M, par, sc, l2g, 60, dt_fixed=dt)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    print("waf", prec, errs)
+    assert max(errs) <= tol, errs
+
+
+@pytest.mark.parametrize("name", ["hllc1", "muscl_minmod_rk2", "waf"])
+def test_lake_at_rest_gpu(name):
+    sc = lake_at_rest()
+    for prec in (1, 0):
+        s, M, par, pr = make_pair(sc, name, precision=prec)
+        s.step(1000)
+        h, hu, hv = s.read_state()
+        wet = h > 1e-6
+        vmax = max(np.abs(hu[wet] / h[wet]).max(), np.abs(hv[wet] / h[wet]).max())
+        print(name, "precision", prec, "max |u| after 1000 steps", vmax)
+        assert vmax <= (1e-12 if prec == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("name", ["hllc1", "muscl_superbee_rk2", "waf"])
+def test_mass_conservation_fp64(name):
+    sc = dam_break_channel(Lx=40.0, Ly=8.0, nx=80, ny=16, x_dam=20.0)
+    s, M, par, pr = make_pair(sc, name, precision=1)
+    A = M.geometry()["area"]
+    m0 = (A * sc.h[pr.sub.l2g]).sum()
+    s.step(500)
+    h, _, _ = s.read_state()
+    assert abs((A * h).sum() - m0) <= 1e-12 * m0
+
+
+def test_graph_and_direct_launches_agree_bitwise():
+    sc = small_river()
+    a, _, _, pr = make_pair(sc, "muscl_minmod_rk2", precision=0)
+    b, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=0, prepared=pr)
+    a.step(12)                      # two captured 6-step graphs
+    for _ in range(12):
+        b.step(1)                   # twelve direct launches
+    for x, y in zip(a.read_state(), b.read_state()):
+        assert np.array_equal(x, y)
+    assert a.time() == b.time()
+
+
+def test_runs_are_deterministic():
+    sc = small_river()
+    outs = []
+    for _ in range(2):
+        s, _, _, pr = make_pair(sc, "muscl_superbee_rk2", precision=0)
+        s.step(50)
+        outs.append(s.read_state())
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
+def test_bad_state_and_mesh_rejected():
+    swe, prepare_scenario = lib()
+    sc = config1()
+    pr = prepare_scenario(sc)
+    s = swe.Solver(precision=1)
+    s.mesh_upload(pr.mesh)
+    h = sc.h[pr.sub.l2g].copy()
+    h[5] = np.nan
+    with pytest.raises(swe.SweError) as e:
+        s.set_state(h, sc.hu, sc.hv)
+    assert e.value.code == -3
+    h[5] = -1.0
+    with pytest.raises(swe.SweError):
+        s.set_state(h, sc.hu, sc.hv)
+    bad = pr.mesh
+    bad.cell_nodes = bad.cell_nodes.copy()
+    bad.cell_nodes[3] = bad.cell_nodes[3][[0, 2, 1]]
+    with pytest.raises(swe.SweError) as e:
+        s.mesh_upload(bad)
+    assert e.value.code == -2
+
+
+def test_full_config2_ten_steps_fp32():
+    """Config 2 at full size (999,824 cells) in the launch configuration the
+    benchmark times: 10 fixed-dt MUSCL-HLLC-RK2 steps against the oracle on
+    every cell."""
+    from swe_inputs import config2
+    sc = config2()
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=0)
+    l2g = pr.sub.l2g
+    dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    g, r = _run_both(s, M, par, sc, l2g, 10, dt_fixed=dt)
+    errs = state_errors(g, r[:3], pr.sub.n_owned)
+    print("config2 full, 10 steps", errs)
+    assert max(errs) <= 1e-4, errs
