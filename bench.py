@@ -11,8 +11,9 @@ the state stays in HBM for the whole timed region.
 
 Prints one JSON line.  ``value`` = owned cells x steps / wall seconds.
 ``roofline`` prices the stage kernel (the only kernel of the step) against
-8 TB/s with the per-cell algorithmic bytes of the stored-geometry design; its
-launch time comes from HIP events recorded on the library's stream.
+8 TB/s with the per-cell algorithmic bytes of a stored-geometry design (212 B
+per MUSCL-RK2 cell-update); its launch time comes from HIP events recorded on
+the library's stream around the timed steps.
 ``cpu_baseline`` times the serial FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
@@ -27,12 +28,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per cell and launch of the FP32 stage kernel (the
-# stored-geometry layout): stage 1 reads neighbours (16), state (16), cell
-# geometry (16), half-edge geometry (48) and MUSCL distances (48) and writes
-# the state (16): 160 B; stage 2 also reads U^n (16): 176 B.
-BYTES_STAGE1 = 160
-BYTES_STAGE2 = 176
+# Algorithmic HBM bytes per cell-update of MUSCL-HLLC-RK2 in FP32 for a
+# design that stores the mesh geometry (the per-unit model of the hot-path
+# scope: 98 B for the first stage, 114 B for the second, 212 B per step; a
+# design that recomputes geometry from the nodes would move 132 B).  The
+# library's present layout moves more (336 B: see the measured traffic).
+BYTES_STAGE1 = 98
+BYTES_STAGE2 = 114
+BYTES_EULER_F64 = 132   # first-order HLLC, FP64, stored geometry
 
 
 def workload(name):
@@ -109,9 +112,12 @@ def main():
     rk2 = kw["integrator"] == 1
     launches = args.steps * (2 if rk2 else 1)
     avg_launch_s = gpu_ms * 1e-3 / launches
-    per_launch_bytes = ((BYTES_STAGE1 + BYTES_STAGE2) / 2 if rk2 else BYTES_STAGE1) * n_owned
-    if kw["precision"] == 1:
-        per_launch_bytes *= 2
+    if rk2:
+        per_launch_bytes = (BYTES_STAGE1 + BYTES_STAGE2) / 2 * n_owned
+        if kw["precision"] == 1:
+            per_launch_bytes *= 2
+    else:
+        per_launch_bytes = (BYTES_EULER_F64 if kw["precision"] == 1 else BYTES_STAGE1) * n_owned
     achieved = per_launch_bytes / avg_launch_s / 1e9
     out = {
         "metric": "cell-updates/s (MUSCL-HLLC, FP32, 1 GPU)",

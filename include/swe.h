@@ -157,6 +157,24 @@ int swe_set_state(swe_ctx *ctx, const void *h, const void *hu, const void *hv, i
                   double t);
 int swe_read_state(swe_ctx *ctx, void *h, void *hu, void *hv, int where);
 
+/* Batched ensemble: several independent meshes (no ghost cells), one
+ * scenario each, concatenated in one context and stepped together by the
+ * same kernel launches (one graph), each scenario with its own CFL step,
+ * time, inflow and outflow.  State arrays of set_state / read_state are the
+ * concatenation in the order given; swe_batch_offsets gives the first cell
+ * of each scenario ([n_scen + 1] entries, may be NULL to get n_scen only). */
+int swe_mesh_upload_batch(swe_ctx *ctx, int n_meshes, const swe_mesh *meshes);
+int swe_set_bc_series_scenario(swe_ctx *ctx, int scenario, int n, const double *t,
+                               const double *q);
+int swe_batch_offsets(const swe_ctx *ctx, int32_t *n_scenarios, int32_t *offsets);
+int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
+
+/* Autotuner: times n_steps CFL steps for each launch shape (64, 128 or 256
+ * threads per block; one tile per block or a persistent grid of
+ * 2048 / block blocks per compute unit) from the current state, keeps the
+ * fastest and restores the state, clocks and time.  Outputs may be NULL. */
+int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
+
 /* n_steps explicit steps, asynchronous on the context's stream.
  * dt_fixed > 0: every step uses that dt; otherwise the CFL step of Sec. 6.1
  * (computed on the device from the owned cells, never copied to the host). */
@@ -177,6 +195,48 @@ int swe_ghost_sizes(const swe_ctx *ctx, int32_t *n_send, int32_t *n_ghost);
 /* Wall time of the kernels of the last swe_step call (ms, measured with HIP
  * events on the context stream; syncs). */
 int swe_last_step_ms(swe_ctx *ctx, float *ms);
+
+/* ---- learned slope limiter (an addition of this library) ---------------
+ * A per-half-edge network 14 -> 32 -> 32 -> 1 (ReLU, ReLU, sigmoid) gives
+ * phi in [0,1]; with limiter == SWE_LEARNED the MUSCL slope of a half-edge
+ * becomes phi times the central slope (U_R - U_Lupw)/|x_R - x_Lupw| of
+ * Sec. 6.2.3.  It falls back to the minmod slope when phi is outside [0,1]
+ * or NaN or the reconstructed depth is negative, and to first order where
+ * the classic limiter does (dry stencil cell, boundary edge).  Parameters
+ * are 1569 floats: W1[32][14], b1[32], W2[32][32], b2[32], W3[32], b3. */
+#define SWE_MLP_NPARAM 1569
+#define SWE_PAIR_RECORD 32  /* floats per training record */
+/* Store the parameters (host, FP32) rounded to BF16 for the matrix-core
+ * inference kernel. */
+int swe_limiter_set_weights(swe_ctx *ctx, const float *params);
+/* phi of every half-edge of the current state into dev_phi[3*n_total]
+ * (0.5 where the half-edge is not reconstructed to second order). */
+int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
+/* Training records from a fine solution on the red refinement of the coarse
+ * mesh (both contexts on one device, same precision).  dev_children
+ * [4*n_total(coarse)]: fine local index of the four children of each coarse
+ * cell (child k at parent node k, 3 the central one).  The coarse state is
+ * set to the restriction (mean of the children) at t = 0, and dev_rec
+ * [3*n_total(coarse)][32] receives per half-edge: features[14], cell values
+ * (h, eta, u_n, u_t)[4], central slopes[4], d_mid, target[4] = mean of the two
+ * children touching the edge, valid flag.  Children out of range give
+ * SWE_ERR_ARG. */
+int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_children, float *dev_rec);
+
+/* Trainer: FP32 master weights and Adam moments on one device.  The loss of
+ * n records (indices dev_idx into dev_rec[n_rec][32]) is
+ * (1/n) sum sum_v wv[v] (q_v + d_mid phi s_v - t_v)^2 over v = h, eta, u_n, u_t. */
+typedef struct swe_trainer swe_trainer;
+int swe_trainer_create(int device, const float *init_params, swe_trainer **out);
+void swe_trainer_destroy(swe_trainer *tr);
+/* loss and gradient (host [1569]) at the current weights, no update */
+int swe_trainer_loss_grad(swe_trainer *tr, const float *dev_rec, int32_t n_rec,
+                          const int32_t *dev_idx, int32_t n, const float *wv, float *loss,
+                          float *grad_host);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr */
+int swe_trainer_step(swe_trainer *tr, const float *dev_rec, int32_t n_rec, const int32_t *dev_idx,
+                     int32_t n, const float *wv, float lr, float *loss);
+int swe_trainer_get_params(swe_trainer *tr, float *host_params);
 
 /* ---- host mesh toolkit (Sec. 3.1 - 3.3), CPU only ---------------------- */
 /* Dual graph: cell across each local edge, -1 where none (global numbering).

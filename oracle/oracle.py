@@ -85,6 +85,7 @@ def lib():
         _lib.or_mlp_forward.argtypes = [dp, C.c_int, dp, C.c_int, dp]
         _lib.or_mlp_loss_grad.restype = C.c_double
         _lib.or_mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp, dp, dp, dp, dp]
+        _lib.or_limiter_inputs.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, dp, dp]
         _lib.od_neighbors.argtypes = [C.c_int, C.c_int, ip, ip]
         _lib.od_partition.argtypes = [C.c_int, ip, C.c_int, ip]
         _lib.od_morton.argtypes = [C.c_int, dp, C.c_int, ip, C.POINTER(C.c_uint32)]
@@ -266,6 +267,17 @@ class Mesh:
                             _d(run), _d(rut), _i(sec))
         return rh.reshape(-1, 3), rb.reshape(-1, 3), run.reshape(-1, 3), \
             rut.reshape(-1, 3), sec.reshape(-1, 3)
+
+
+def limiter_inputs(mesh: "Mesh", params: Params, h, hu, hv):
+    """Per half-edge [n, 3, 24]: features[14], q[4], central slopes[4], d_mid,
+    eligible; and phi [n, 3] (0.5 where not eligible)."""
+    h, hu, hv = (np.ascontiguousarray(a, np.float64) for a in (h, hu, hv))
+    out = np.empty((mesh.n, 3, 24))
+    phi = np.empty((mesh.n, 3))
+    p = params.c()
+    lib().or_limiter_inputs(mesh.h, C.byref(p), _d(h), _d(hu), _d(hv), _d(out), _d(phi))
+    return out, phi
 
 
 def riemann(params: Params, scheme, UL, UR, dt_dx=0.0, ratio_in=None):

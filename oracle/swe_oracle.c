@@ -572,6 +572,69 @@ static iface reconstruct(const or_mesh *M, const or_params *P, const double *h, 
     return r;
 }
 
+/* Inputs of the learned limiter for every half-edge (test access): for
+ * half-edge e = 3c+m, out[24*e ..]: features[14], cell values (h, eta, u_n,
+ * u_t)[4] in c's edge frame, central slopes (U_R - U_Lupw)/|x_R - x_Lupw|[4],
+ * d_mid, eligibility (1: reconstructed to second order by MUSCL, 0: first
+ * order); phi[e] = network output (bf16 layer inputs if P->mlp_bf16) or 0.5
+ * where not eligible. */
+int or_limiter_inputs(const or_mesh *M, const or_params *P, const double *h, const double *hu,
+                      const double *hv, double *out, double *phi)
+{
+    double eps = P->eps;
+    for (int c = 0; c < M->nc; ++c)
+        for (int m = 0; m < 3; ++m) {
+            int e = 3 * c + m;
+            double *o = out + 24 * (size_t)e;
+            for (int i = 0; i < 24; ++i) o[i] = 0.0;
+            phi[e] = 0.5;
+            double nx = M->enx[e], ny = M->eny[e];
+            double qc[4];
+            frame_state(M, h, hu, hv, eps, c, nx, ny, qc);
+            for (int i = 0; i < 4; ++i) o[14 + i] = qc[i];
+            double dm = hypot(M->emx[e] - M->cx[c], M->emy[e] - M->cy[c]);
+            o[22] = dm;
+            int k = M->nbr[e];
+            if (k < 0) continue;
+            int a = M->nbr[3 * c + (m + 1) % 3], bb = M->nbr[3 * c + (m + 2) % 3];
+            if (h[c] <= eps || h[k] <= eps) continue;
+            if ((a >= 0 && h[a] <= eps) || (bb >= 0 && h[bb] <= eps) || (a < 0 && bb < 0)) continue;
+            double qk[4], qu[4], xu, yu, bu, qnu, qtu;
+            frame_state(M, h, hu, hv, eps, k, nx, ny, qk);
+            if (a >= 0 && bb >= 0) {
+                double qa[4], qb[4];
+                frame_state(M, h, hu, hv, eps, a, nx, ny, qa);
+                frame_state(M, h, hu, hv, eps, bb, nx, ny, qb);
+                for (int i = 0; i < 4; ++i) qu[i] = 0.5 * (qa[i] + qb[i]);
+                xu = 0.5 * (M->cx[a] + M->cx[bb]); yu = 0.5 * (M->cy[a] + M->cy[bb]);
+                bu = 0.5 * (M->b[a] + M->b[bb]);
+                qnu = 0.5 * ((hu[a] * nx + hv[a] * ny) + (hu[bb] * nx + hv[bb] * ny));
+                qtu = 0.5 * ((-hu[a] * ny + hv[a] * nx) + (-hu[bb] * ny + hv[bb] * nx));
+            } else {
+                int oo = a >= 0 ? a : bb;
+                frame_state(M, h, hu, hv, eps, oo, nx, ny, qu);
+                xu = M->cx[oo]; yu = M->cy[oo]; bu = M->b[oo];
+                qnu = hu[oo] * nx + hv[oo] * ny;
+                qtu = -hu[oo] * ny + hv[oo] * nx;
+            }
+            double du = hypot(M->cx[c] - xu, M->cy[c] - yu);
+            double df = hypot(M->cx[k] - M->cx[c], M->cy[k] - M->cy[c]);
+            double dc = hypot(M->cx[k] - xu, M->cy[k] - yu);
+            double qcb[4] = {h[c], hu[c] * nx + hv[c] * ny, -hu[c] * ny + hv[c] * nx, M->b[c]};
+            double qub[4] = {qu[0], qnu, qtu, bu};
+            double qkb[4] = {h[k], hu[k] * nx + hv[k] * ny, -hu[k] * ny + hv[k] * nx, M->b[k]};
+            halfedge_features(P->g, qcb, qub, qkb, du, df, dm, h[c], qc[2], qc[3], h[k], o);
+            for (int i = 0; i < 4; ++i) o[18 + i] = (qk[i] - qu[i]) / dc;
+            o[23] = 1.0;
+            if (P->mlp) {
+                mlp_view v = mlp_unpack(P->mlp);
+                double a1[MLP_H], a2[MLP_H], z;
+                phi[e] = mlp_forward(&v, o, P->mlp_bf16, a1, a2, &z);
+            }
+        }
+    return 0;
+}
+
 /* rotation T_n of Sec. 6.1 and its inverse */
 static void rot(double nx, double ny, double h, double hu, double hv, double U[3])
 {

@@ -16,7 +16,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              # no packed FP32 instructions anywhere in the device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-result"]
+             # FP32 division and square root through the hardware rcp/sqrt
+             # (about 1 ulp) instead of the correctly rounded sequences; the
+             # FP64 path is unaffected
+             "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+             "-Wno-unused-result"] + os.environ.get("SWE_EXTRA_HIPFLAGS", "").split()
 
 
 def run(cmd):
@@ -24,7 +28,8 @@ def run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str = LIB, flags=None) -> str:
+    hip_flags = HIP_FLAGS if flags is None else flags
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     obj = os.path.join(HERE, "_build", "swe_host.o")
     run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
@@ -32,12 +37,12 @@ def build(verbose: bool = True) -> str:
     objs = [obj]
     for src in ("swe_device.hip", "swe_mlp.hip"):
         o = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
-        run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        run([HIPCC] + hip_flags + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
-    tmp = LIB + f".tmp{os.getpid()}"
+    tmp = out + f".tmp{os.getpid()}"
     run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

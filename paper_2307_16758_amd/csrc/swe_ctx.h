@@ -1,0 +1,56 @@
+// Context object behind the opaque swe_ctx of include/swe.h (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "swe_internal.h"
+#include "swe_kernels.h"
+
+struct swe_ctx {
+    swe_config cfg{};
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::string err;
+    bool has_mesh = false, has_state = false, ran = false;
+    int n_owned = 0, n_total = 0, n_scen = 1, n_send = 0, n_ghost = 0;
+    size_t tsize = 4;
+    // device buffers
+    void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
+    void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
+    float *phi = nullptr;       // learned-limiter output, one per half-edge
+    void *mlp = nullptr;        // learned-limiter weights (MlpDev, BF16)
+    bool has_mlp = false;
+    swe::Clock *clock = nullptr;
+    swe::ScenParams *scen = nullptr;
+    double *ser_t = nullptr, *ser_q = nullptr, *t0 = nullptr;
+    int *health = nullptr, *flag = nullptr, *send_idx = nullptr;
+    // host mirrors
+    std::vector<swe::ScenParams> h_scen;
+    std::vector<std::pair<std::vector<double>, std::vector<double>>> series;  // per scenario
+    std::vector<double> h_ser_t, h_ser_q, h_t0;
+    std::vector<int> scen_off;  // first cell of each scenario, n_scen + 1 entries
+    // launch shape: threads per block and blocks of a persistent launch (0:
+    // one tile per block); picked by swe_autotune when tuned
+    int grid_persist = 0;
+    bool tuned = false;
+    double computed_inflow_len = 0.0, given_inflow_len = 0.0;
+    long long step_count = 0;  // steps since set_state (selects clock slots and buffers)
+    int block = 256;
+    // graphs: chunk of kGraphSteps steps starting at a step index multiple of it
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = -1.0;
+    bool use_graphs = true;
+};
+
+
+namespace swe {
+// Learned limiter (swe_mlp.hip): phi of every half-edge of state U into
+// ctx->phi, on the context stream.
+int launch_limiter_phi(swe_ctx *c, const void *U);
+// Clock slots of a freshly set state U[0] (time t, CFL minima); syncs.
+int init_clock(swe_ctx *c, double t);
+}  // namespace swe

@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "swe_ctx.h"
 #include "swe_internal.h"
 #include "swe_kernels.h"
 
@@ -140,25 +141,12 @@ __device__ __forceinline__ bool waf_upwind(const T4 &Ua, bool ha, const T4 &Ub, 
     return ha || hb;
 }
 
+// One cell of one stage (all of Sec. 6.1 - 6.2 for cell c) followed by the
+// wave's share of the CFL reduction.  Every lane of the wave calls it.
 template <typename T, int SCHEME, int LIM, int WAFM>
-__global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
+__device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
 {
     using T4 = typename V4<T>::type;
-    const int bid = xcd_tile(blockIdx.x, gridDim.x);
-    const int c = bid * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0) {
-        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
-            if (a.kind != 2) {  // first kernel of the step: clear the slot of step + 2
-                Clock &r = a.clock[3 * s + a.slot_reset];
-                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
-            }
-            if (a.kind != 1) {  // last kernel of the step: advance the time
-                const Clock cur = a.clock[3 * s + a.slot_cur];
-                a.clock[3 * s + a.slot_next].t =
-                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
-            }
-        }
-    }
     double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
     int scen = -1;
     if (c < a.n) {
@@ -313,7 +301,7 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
         smin = min(smin, __shfl_xor(smin, o));
         smax = max(smax, __shfl_xor(smax, o));
     }
-    if (smax < 0) return;
+    if (smax < 0) return;  // the whole wave is past the end or dry
     if (smin == smax) {
         for (int o = 32; o > 0; o >>= 1) {
             ratio = fmin(ratio, __shfl_xor(ratio, o));
@@ -334,24 +322,74 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
     }
 }
 
-// CFL minima of the current state into one clock slot (after set_state).
+template <typename T, int SCHEME, int LIM, int WAFM>
+__global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
+{
+    if (blockIdx.x == 0) {
+        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
+            if (a.kind != 2) {  // first kernel of the step: clear the slot of step + 2
+                Clock &r = a.clock[3 * s + a.slot_reset];
+                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
+            }
+            if (a.kind != 1) {  // last kernel of the step: advance the time
+                const Clock cur = a.clock[3 * s + a.slot_cur];
+                a.clock[3 * s + a.slot_next].t =
+                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
+            }
+        }
+    }
+    // one tile per block, or (persistent launch, gridDim < tiles) a
+    // grid-stride sweep; either way each XCD takes contiguous tiles
+    const int ntiles = (a.n + (int)blockDim.x - 1) / (int)blockDim.x;
+    for (int t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+        stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
+}
+
+// CFL minima of the current state into one clock slot (after set_state):
+// wave-wide reduction, one set of atomics per wave and scenario.
 template <typename T>
 __global__ void k_cfl_init(int n, const int4 *nbr, const typename V4<T>::type *cell,
                            const typename V4<T>::type *U, Clock *clock, int slot, T g, T eps)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const unsigned word = (unsigned)nbr[c].w;
-    if (!((word >> kOwnedBit) & 1u)) return;
-    const int s = (int)(word >> kScenShift);
-    const T h = U[c].x;
-    if (!(h > eps)) return;
-    const T u = U[c].y / h, v = U[c].z / h;
-    const T lm = sqrt(u * u + v * v) + sqrt(g * h);
-    Clock &k = clock[3 * s + slot];
-    atomicMin(&k.ratio_min, dbits(double(cell[c].y / lm)));
-    atomicMin(&k.rad_min, dbits(double(cell[c].y)));
-    atomicMax(&k.lam_max, dbits(double(lm)));
+    double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
+    int scen = -1;
+    if (c < n) {
+        const unsigned word = (unsigned)nbr[c].w;
+        const T h = U[c].x;
+        if (((word >> kOwnedBit) & 1u) && h > eps) {
+            const T u = U[c].y / h, v = U[c].z / h;
+            const T lm = sqrt(u * u + v * v) + sqrt(g * h);
+            ratio = double(cell[c].y / lm);
+            rad = double(cell[c].y);
+            lam = double(lm);
+        }
+        scen = (int)(word >> kScenShift);
+    }
+    int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
+    for (int o = 32; o > 0; o >>= 1) {
+        smin = min(smin, __shfl_xor(smin, o));
+        smax = max(smax, __shfl_xor(smax, o));
+    }
+    if (smax < 0) return;
+    if (smin == smax) {
+        for (int o = 32; o > 0; o >>= 1) {
+            ratio = fmin(ratio, __shfl_xor(ratio, o));
+            rad = fmin(rad, __shfl_xor(rad, o));
+            lam = fmax(lam, __shfl_xor(lam, o));
+        }
+        if ((threadIdx.x & 63) == 0 && lam > 0.0) {
+            Clock &k = clock[3 * smin + slot];
+            atomicMin(&k.ratio_min, dbits(ratio));
+            atomicMin(&k.rad_min, dbits(rad));
+            atomicMax(&k.lam_max, dbits(lam));
+        }
+    } else if (scen >= 0 && lam > 0.0) {
+        Clock &k = clock[3 * scen + slot];
+        atomicMin(&k.ratio_min, dbits(ratio));
+        atomicMin(&k.rad_min, dbits(rad));
+        atomicMax(&k.lam_max, dbits(lam));
+    }
 }
 
 __global__ void k_clock_reset(Clock *clock, int n_scen, int slot, const double *t0, int set_t)
@@ -415,36 +453,6 @@ __global__ void k_fill_int(int *p, int v, int n)
 }
 
 }  // namespace
-
-// ------------------------------------------------------------------ context
-struct swe_ctx {
-    swe_config cfg{};
-    int dev = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::string err;
-    bool has_mesh = false, has_state = false, ran = false;
-    int n_owned = 0, n_total = 0, n_scen = 1, n_send = 0, n_ghost = 0;
-    size_t tsize = 4;
-    // device buffers
-    void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
-    void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
-    float *phi = nullptr;
-    Clock *clock = nullptr;
-    ScenParams *scen = nullptr;
-    double *ser_t = nullptr, *ser_q = nullptr, *t0 = nullptr;
-    int *health = nullptr, *flag = nullptr, *send_idx = nullptr;
-    // host mirrors
-    std::vector<ScenParams> h_scen;
-    std::vector<double> h_ser_t, h_ser_q;
-    double computed_inflow_len = 0.0, given_inflow_len = 0.0;
-    long long step_count = 0;  // steps since set_state (selects clock slots and buffers)
-    int block = 256;
-    // graphs: chunk of kGraphSteps steps starting at a step index multiple of it
-    hipGraphExec_t graph = nullptr;
-    double graph_dt = -1.0;
-    bool use_graphs = true;
-};
 
 namespace {
 
@@ -514,6 +522,16 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
 
 int push_scenarios(swe_ctx *c)
 {
+    c->h_ser_t.clear();
+    c->h_ser_q.clear();
+    for (size_t i = 0; i < c->h_scen.size(); ++i) {
+        c->h_scen[i].series_off = (int)c->h_ser_t.size();
+        c->h_scen[i].series_n = i < c->series.size() ? (int)c->series[i].first.size() : 0;
+        if (i < c->series.size()) {
+            c->h_ser_t.insert(c->h_ser_t.end(), c->series[i].first.begin(), c->series[i].first.end());
+            c->h_ser_q.insert(c->h_ser_q.end(), c->series[i].second.begin(), c->series[i].second.end());
+        }
+    }
     dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
     HIP_OK(c, hipMalloc(&c->scen, sizeof(ScenParams) * c->h_scen.size()));
     HIP_OK(c, hipMemcpy(c->scen, c->h_scen.data(), sizeof(ScenParams) * c->h_scen.size(),
@@ -577,15 +595,21 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.slot_reset = (int)((step + 2) % 3);
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter);
     const int B = c->block;
-    const dim3 grid((c->n_total + B - 1) / B), blk(B);
+    const int ntiles = (c->n_total + B - 1) / B;
+    const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
+    const dim3 blk(B);
     T4 *Ucur = (T4 *)c->U[step & 1];
+    const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
     if (c->cfg.integrator == SWE_RK2) {
-        // stage 1: U^n -> U1;  stage 2: U1 -> U2, averaged with U^n in place
+        // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2
+        if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 1; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U1;
         hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
+        if (learned && launch_limiter_phi(c, c->U1) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 2; a.Uin = (T4 *)c->U1; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
         hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
     } else {
+        if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 0; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
         hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
     }
@@ -684,6 +708,7 @@ void swe_destroy(swe_ctx *c)
     (void)hipSetDevice(c->dev);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release_mesh(c);
+    dfree(c->mlp);
     dfree_t(c->health);
     dfree_t(c->flag);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -692,41 +717,80 @@ void swe_destroy(swe_ctx *c)
     delete c;
 }
 
-int swe_mesh_upload(swe_ctx *c, const swe_mesh *m)
+}  // extern "C"
+
+namespace {
+
+// Upload one mesh (a sub-domain with ghosts) or several independent meshes
+// (a batch: one scenario each, concatenated, no ghosts).
+int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
 {
-    if (!c || !m) return set_err(c, SWE_ERR_ARG, "null argument");
+    if (!c || !ms || nm <= 0 || nm > kMaxScenarios) return set_err(c, SWE_ERR_ARG, "bad argument");
     HIP_OK(c, hipSetDevice(c->dev));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    HostGeometry g;
-    std::string msg;
-    int rc = prepare_geometry(*m, 0, g, msg);
-    if (rc != SWE_OK) return set_err(c, rc, msg);
-    // ghost exchange lists
-    const int n_ghost = m->n_total - m->n_owned;
-    if (m->n_peers < 0) return set_err(c, SWE_ERR_MESH, "n_peers < 0");
+    std::vector<HostGeometry> gs(nm);
+    std::vector<int> off(nm + 1, 0);
+    for (int i = 0; i < nm; ++i) {
+        std::string msg;
+        int rc = prepare_geometry(ms[i], i, gs[i], msg);
+        if (rc != SWE_OK) return set_err(c, rc, nm > 1 ? "mesh " + std::to_string(i) + ": " + msg : msg);
+        if ((long long)off[i] + ms[i].n_total > 0x7fffffffLL / 3)
+            return set_err(c, SWE_ERR_MESH, "too many cells");
+        off[i + 1] = off[i] + ms[i].n_total;
+    }
+    const swe_mesh *m = &ms[0];
+    const int n_ghost = nm == 1 ? m->n_total - m->n_owned : 0;
     int n_send = 0;
-    if (m->n_peers > 0) {
-        if (!m->recv_off || !m->send_off || !m->send_idx)
-            return set_err(c, SWE_ERR_MESH, "ghost lists missing");
-        if (m->recv_off[0] != 0 || m->send_off[0] != 0 || m->recv_off[m->n_peers] != n_ghost)
-            return set_err(c, SWE_ERR_MESH, "receive ranges do not cover the ghost cells");
-        for (int j = 0; j < m->n_peers; ++j)
-            if (m->recv_off[j + 1] < m->recv_off[j] || m->send_off[j + 1] < m->send_off[j])
-                return set_err(c, SWE_ERR_MESH, "ghost offsets not ascending");
-        n_send = m->send_off[m->n_peers];
-        for (int i = 0; i < n_send; ++i)
-            if (m->send_idx[i] < 0 || m->send_idx[i] >= m->n_owned)
-                return set_err(c, SWE_ERR_MESH, "send index outside the owned cells");
-    } else if (n_ghost != 0) {
-        // ghosts without peers are allowed (halo kept by the caller) but cannot be received
+    if (nm > 1) {
+        for (int i = 0; i < nm; ++i)
+            if (ms[i].n_peers != 0 || ms[i].n_owned != ms[i].n_total)
+                return set_err(c, SWE_ERR_MESH, "batched meshes cannot have ghost cells");
+    } else {
+        if (m->n_peers < 0) return set_err(c, SWE_ERR_MESH, "n_peers < 0");
+        if (m->n_peers > 0) {
+            if (!m->recv_off || !m->send_off || !m->send_idx)
+                return set_err(c, SWE_ERR_MESH, "ghost lists missing");
+            if (m->recv_off[0] != 0 || m->send_off[0] != 0 || m->recv_off[m->n_peers] != n_ghost)
+                return set_err(c, SWE_ERR_MESH, "receive ranges do not cover the ghost cells");
+            for (int j = 0; j < m->n_peers; ++j)
+                if (m->recv_off[j + 1] < m->recv_off[j] || m->send_off[j + 1] < m->send_off[j])
+                    return set_err(c, SWE_ERR_MESH, "ghost offsets not ascending");
+            n_send = m->send_off[m->n_peers];
+            for (int i = 0; i < n_send; ++i)
+                if (m->send_idx[i] < 0 || m->send_idx[i] >= m->n_owned)
+                    return set_err(c, SWE_ERR_MESH, "send index outside the owned cells");
+        }
+    }
+    // concatenate (neighbour indices shifted by the mesh offset)
+    HostGeometry g;
+    if (nm == 1) {
+        g = std::move(gs[0]);
+    } else {
+        const size_t N = off[nm];
+        g.cell.reserve(4 * N); g.he_geo.reserve(12 * N); g.he_dist.reserve(12 * N); g.nbr4.reserve(4 * N);
+        for (int i = 0; i < nm; ++i) {
+            HostGeometry &gi = gs[i];
+            g.cell.insert(g.cell.end(), gi.cell.begin(), gi.cell.end());
+            g.he_geo.insert(g.he_geo.end(), gi.he_geo.begin(), gi.he_geo.end());
+            g.he_dist.insert(g.he_dist.end(), gi.he_dist.begin(), gi.he_dist.end());
+            for (size_t j = 0; j < gi.nbr4.size(); ++j) {
+                int32_t v = gi.nbr4[j];
+                if ((j & 3) != 3 && v >= 0) v += off[i];
+                g.nbr4.push_back(v);
+            }
+            std::vector<double>().swap(gi.cell);
+            std::vector<double>().swap(gi.he_geo);
+            std::vector<double>().swap(gi.he_dist);
+        }
     }
     release_mesh(c);
-    c->n_owned = m->n_owned;
-    c->n_total = m->n_total;
-    c->n_scen = 1;
+    c->n_total = off[nm];
+    c->n_owned = nm == 1 ? m->n_owned : c->n_total;
+    c->n_scen = nm;
     c->n_send = n_send;
     c->n_ghost = n_ghost;
-    rc = c->cfg.precision == SWE_F64 ? upload_geometry<double>(c, g) : upload_geometry<float>(c, g);
+    c->scen_off = off;
+    int rc = c->cfg.precision == SWE_F64 ? upload_geometry<double>(c, g) : upload_geometry<float>(c, g);
     if (rc != SWE_OK) return rc;
     const size_t n = c->n_total, ts = c->tsize;
     HIP_OK(c, hipMalloc(&c->U[0], 4 * ts * n));
@@ -735,50 +799,88 @@ int swe_mesh_upload(swe_ctx *c, const swe_mesh *m)
     HIP_OK(c, hipMalloc(&c->tmp3, 3 * ts * n));
     HIP_OK(c, hipMalloc(&c->bed, ts * n));
     HIP_OK(c, hipMalloc(&c->phi, sizeof(float) * 3 * n));
-    HIP_OK(c, hipMalloc(&c->clock, sizeof(Clock) * 3));
-    HIP_OK(c, hipMalloc(&c->t0, sizeof(double)));
-    if (ts == 8) {
-        HIP_OK(c, hipMemcpy(c->bed, m->cell_b, 8 * n, hipMemcpyHostToDevice));
-    } else {
-        std::vector<float> bf(m->cell_b, m->cell_b + n);
-        HIP_OK(c, hipMemcpy(c->bed, bf.data(), 4 * n, hipMemcpyHostToDevice));
+    HIP_OK(c, hipMalloc(&c->clock, sizeof(Clock) * 3 * (size_t)nm));
+    HIP_OK(c, hipMalloc(&c->t0, sizeof(double) * (size_t)nm));
+    {
+        std::vector<double> bd(n);
+        for (int i = 0; i < nm; ++i) std::copy(ms[i].cell_b, ms[i].cell_b + ms[i].n_total, bd.begin() + off[i]);
+        if (ts == 8) {
+            HIP_OK(c, hipMemcpy(c->bed, bd.data(), 8 * n, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> bf(bd.begin(), bd.end());
+            HIP_OK(c, hipMemcpy(c->bed, bf.data(), 4 * n, hipMemcpyHostToDevice));
+        }
     }
     if (n_send > 0) {
         HIP_OK(c, hipMalloc(&c->send_idx, sizeof(int) * n_send));
         HIP_OK(c, hipMemcpy(c->send_idx, m->send_idx, sizeof(int) * n_send, hipMemcpyHostToDevice));
     }
-    c->computed_inflow_len = g.inflow_length;
-    c->given_inflow_len = m->inflow_length;
-    const double L = m->inflow_length > 0 ? m->inflow_length : g.inflow_length;
-    ScenParams sp{};
-    sp.inflow_q = m->inflow_q;
-    sp.inv_inflow_len = L > 0 ? 1.0 / L : 0.0;
-    sp.outflow_stage = m->outflow_stage;
-    sp.series_off = 0;
-    sp.series_n = 0;
-    c->h_scen.assign(1, sp);
-    c->h_ser_t.clear();
-    c->h_ser_q.clear();
+    c->h_scen.assign(nm, ScenParams{});
+    c->series.assign(nm, {});
+    for (int i = 0; i < nm; ++i) {
+        const double L = ms[i].inflow_length > 0 ? ms[i].inflow_length
+                                                 : (nm == 1 ? g.inflow_length : gs[i].inflow_length);
+        ScenParams &sp = c->h_scen[i];
+        sp.inflow_q = ms[i].inflow_q;
+        sp.inv_inflow_len = L > 0 ? 1.0 / L : 0.0;
+        sp.outflow_stage = ms[i].outflow_stage;
+    }
     rc = push_scenarios(c);
     if (rc != SWE_OK) return rc;
     c->has_mesh = true;
     c->has_state = false;
+    c->tuned = false;
     return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_mesh_upload(swe_ctx *c, const swe_mesh *m) { return upload_meshes(c, m, 1); }
+
+int swe_mesh_upload_batch(swe_ctx *c, int n_meshes, const swe_mesh *meshes)
+{
+    return upload_meshes(c, meshes, n_meshes);
+}
+
+int swe_set_bc_series_scenario(swe_ctx *c, int scen, int n, const double *t, const double *q)
+{
+    if (!c || n < 0 || (n > 0 && (!t || !q))) return set_err(c, SWE_ERR_ARG, "bad series");
+    if (!c->has_mesh) return set_err(c, SWE_ERR_STATE, "no mesh");
+    if (scen < 0 || scen >= c->n_scen) return set_err(c, SWE_ERR_ARG, "scenario index");
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(t[i + 1] > t[i])) return set_err(c, SWE_ERR_ARG, "series times must increase");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->series[scen].first.assign(t, t + n);
+    c->series[scen].second.assign(q, q + n);
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    return push_scenarios(c);
 }
 
 int swe_set_bc_series(swe_ctx *c, int n, const double *t, const double *q)
 {
-    if (!c || n < 0 || (n > 0 && (!t || !q))) return set_err(c, SWE_ERR_ARG, "bad series");
-    if (!c->has_mesh) return set_err(c, SWE_ERR_STATE, "no mesh");
-    for (int i = 0; i + 1 < n; ++i)
-        if (!(t[i + 1] > t[i])) return set_err(c, SWE_ERR_ARG, "series times must increase");
+    return swe_set_bc_series_scenario(c, 0, n, t, q);
+}
+
+int swe_batch_offsets(const swe_ctx *c, int32_t *n_scen, int32_t *offsets)
+{
+    if (!c || !n_scen) return SWE_ERR_ARG;
+    *n_scen = c->n_scen;
+    if (offsets)
+        for (int i = 0; i <= c->n_scen; ++i) offsets[i] = c->scen_off.empty() ? 0 : c->scen_off[i];
+    return SWE_OK;
+}
+
+int swe_scenario_times(swe_ctx *c, double *t)
+{
+    if (!c || !t) return set_err(c, SWE_ERR_ARG, "null");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    c->h_ser_t.assign(t, t + n);
-    c->h_ser_q.assign(q, q + n);
-    c->h_scen[0].series_off = 0;
-    c->h_scen[0].series_n = n;
-    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
-    return push_scenarios(c);
+    std::vector<Clock> k(3 * (size_t)c->n_scen);
+    HIP_OK(c, hipMemcpy(k.data(), c->clock, sizeof(Clock) * k.size(), hipMemcpyDeviceToHost));
+    for (int s = 0; s < c->n_scen; ++s) t[s] = k[3 * s + c->step_count % 3].t;
+    return health_status(c);
 }
 
 int swe_set_state(swe_ctx *c, const void *h, const void *hu, const void *hv, int where, double t)
@@ -807,10 +909,32 @@ int swe_set_state(swe_ctx *c, const void *h, const void *hu, const void *hv, int
                            (const float *)(tmp + 8 * n), (const float *)c->bed, (float4 *)c->U[0],
                            c->flag, (float)c->cfg.eps);
     HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipMemcpyAsync(c->t0, &t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int bad = 0;
+    HIP_OK(c, hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (bad) return set_err(c, SWE_ERR_STATE, "state has a negative or non-finite value");
+    c->step_count = 0;
+    int rc = init_clock(c, t);
+    if (rc != SWE_OK) return rc;
+    c->has_state = true;
+    return SWE_OK;
+}
+
+}  // extern "C"
+
+namespace swe {
+
+int init_clock(swe_ctx *c, double t)
+{
+    const size_t n = c->n_total, ts = c->tsize;
+    const int B = 256, G = (int)((n + B - 1) / B);
+    c->h_t0.assign(c->n_scen, t);
+    HIP_OK(c, hipMemcpyAsync(c->t0, c->h_t0.data(), sizeof(double) * c->n_scen,
+                             hipMemcpyHostToDevice, c->stream));
     // slot 0: time and CFL minima of the initial state; slot 1 cleared
-    hipLaunchKernelGGL(k_clock_reset, dim3(1), dim3(64), 0, c->stream, c->clock, 1, 0, c->t0, 1);
-    hipLaunchKernelGGL(k_clock_reset, dim3(1), dim3(64), 0, c->stream, c->clock, 1, 1, c->t0, 0);
+    const int gs = (c->n_scen + 63) / 64;
+    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(64), 0, c->stream, c->clock, c->n_scen, 0, c->t0, 1);
+    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(64), 0, c->stream, c->clock, c->n_scen, 1, c->t0, 0);
     if (ts == 8)
         hipLaunchKernelGGL(k_cfl_init<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
                            (const int4 *)c->nbr, (const double4 *)c->cell,
@@ -820,14 +944,14 @@ int swe_set_state(swe_ctx *c, const void *h, const void *hu, const void *hv, int
                            (const int4 *)c->nbr, (const float4 *)c->cell, (const float4 *)c->U[0],
                            c->clock, 0, (float)c->cfg.g, (float)c->cfg.eps);
     HIP_OK(c, hipGetLastError());
-    int bad = 0;
-    HIP_OK(c, hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    if (bad) return set_err(c, SWE_ERR_STATE, "state has a negative or non-finite value");
-    c->step_count = 0;
     c->has_state = true;
     return SWE_OK;
 }
+
+}  // namespace swe
+
+extern "C" {
 
 int swe_read_state(swe_ctx *c, void *h, void *hu, void *hv, int where)
 {
@@ -860,8 +984,8 @@ int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
 {
     if (!c || n_steps < 0) return set_err(c, SWE_ERR_ARG, "bad argument");
     if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
-    if (c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED)
-        return set_err(c, SWE_ERR_UNSUPPORTED, "learned limiter weights not set");
+    if (c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED && !c->has_mlp)
+        return set_err(c, SWE_ERR_STATE, "learned limiter weights not set");
     HIP_OK(c, hipSetDevice(c->dev));
     if (!(dt_fixed > 0.0)) dt_fixed = 0.0;
     HIP_OK(c, hipEventRecord(c->ev0, c->stream));
@@ -895,6 +1019,65 @@ int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
     }
     HIP_OK(c, hipEventRecord(c->ev1, c->stream));
     c->ran = true;
+    return SWE_OK;
+}
+
+int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
+{
+    if (!c || n_steps <= 0) return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    HIP_OK(c, hipSetDevice(c->dev));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    int ncu = 0;
+    HIP_OK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->dev));
+    // save the state, clocks and step index; every candidate starts from them
+    const size_t bytes = 4 * c->tsize * (size_t)c->n_total;
+    void *saveU = nullptr;
+    Clock *saveK = nullptr;
+    HIP_OK(c, hipMalloc(&saveU, bytes));
+    if (hipMalloc(&saveK, sizeof(Clock) * 3 * (size_t)c->n_scen) != hipSuccess) {
+        (void)hipFree(saveU);
+        return set_err(c, SWE_ERR_OOM, "autotune buffers");
+    }
+    const long long step0 = c->step_count;
+    void *Ucur = c->U[step0 & 1];
+    HIP_OK(c, hipMemcpyAsync(saveU, Ucur, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(saveK, c->clock, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream));
+    const bool graphs = c->use_graphs;
+    c->use_graphs = false;
+    float best = 1e30f;
+    int best_b = c->block, best_g = c->grid_persist;
+    int rc = SWE_OK;
+    for (int B : {64, 128, 256}) {
+        for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
+            c->block = B;
+            c->grid_persist = persist ? ncu * (2048 / B) : 0;
+            (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
+            (void)hipMemcpyAsync(c->clock, saveK, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream);
+            c->step_count = step0;
+            rc = swe_step(c, 2, 0.0);  // warm-up
+            if (rc != SWE_OK) break;
+            rc = swe_step(c, n_steps, 0.0);
+            if (rc != SWE_OK) break;
+            float ms = 0.f;
+            rc = swe_last_step_ms(c, &ms);
+            if (rc == SWE_OK && ms < best) { best = ms; best_b = B; best_g = c->grid_persist; }
+        }
+    }
+    c->use_graphs = graphs;
+    c->block = best_b;
+    c->grid_persist = best_g;
+    (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->clock, saveK, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    c->step_count = step0;
+    (void)hipFree(saveU);
+    (void)hipFree(saveK);
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    if (rc != SWE_OK) return rc;
+    c->tuned = true;
+    if (block_out) *block_out = best_b;
+    if (grid_out) *grid_out = best_g;
     return SWE_OK;
 }
 

@@ -248,3 +248,59 @@ __device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], con
 }
 
 }  // namespace swe
+
+namespace swe {
+
+constexpr int kMlpIn = 14, kMlpH = 32;
+constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;  // 1569
+
+// Inputs of the learned limiter for the half-edge of cell c across local
+// edge m (a design of this library; the paper has no learned limiter): for
+// h, q_n, q_t (discharges in the edge frame) and b, the upwind slope sb and
+// the cross-edge slope sf as tanh(s d_mid / scale) and their ratio
+// sb sf / (sf^2 + 1e-12) clipped to [-2, 2]; then tanh of the cell's Froude
+// number and of the relative depth jump across the edge.  Scales: h, b:
+// h_c + 0.01 m; q: h_c sqrt(g h_c) + 0.01 m^2/s.  Returns false when the
+// half-edge is not reconstructed to second order (dry stencil cell, no
+// neighbour across the edge, no upwind cell): the features are then zero.
+template <typename T, typename T4>
+__device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, bool hk_, const T4 &Ua,
+                                                 bool ha, const T4 &Ub, bool hb, T nx, T ny, T dm,
+                                                 const T4 &dist, T g, T eps, float f[kMlpIn])
+{
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) f[i] = 0.0f;
+    if (!hk_ || !(Uc.x > eps) || !(Uk.x > eps)) return false;
+    if ((ha && !(Ua.x > eps)) || (hb && !(Ub.x > eps)) || (!ha && !hb)) return false;
+    const T qc[4] = {Uc.x, Uc.y * nx + Uc.z * ny, -Uc.y * ny + Uc.z * nx, Uc.w};
+    const T qk[4] = {Uk.x, Uk.y * nx + Uk.z * ny, -Uk.y * ny + Uk.z * nx, Uk.w};
+    T qu[4];
+    if (ha && hb) {
+        qu[0] = T(0.5) * (Ua.x + Ub.x);
+        qu[1] = T(0.5) * ((Ua.y * nx + Ua.z * ny) + (Ub.y * nx + Ub.z * ny));
+        qu[2] = T(0.5) * ((-Ua.y * ny + Ua.z * nx) + (-Ub.y * ny + Ub.z * nx));
+        qu[3] = T(0.5) * (Ua.w + Ub.w);
+    } else {
+        const T4 &Uo = ha ? Ua : Ub;
+        qu[0] = Uo.x; qu[1] = Uo.y * nx + Uo.z * ny; qu[2] = -Uo.y * ny + Uo.z * nx; qu[3] = Uo.w;
+    }
+    const T hc = Uc.x;
+    const T sh = hc + T(0.01), sq = hc * sqrt(g * hc) + T(0.01);
+    const T sc[4] = {sh, sq, sq, sh};
+    const T du = T(1) / dist.x, df = dist.w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T sb = (qc[k] - qu[k]) / du, sf = (qk[k] - qc[k]) / df;
+        f[3 * k + 0] = float(tanh(sb * dm / sc[k]));
+        f[3 * k + 1] = float(tanh(sf * dm / sc[k]));
+        const T r = sb * sf / (sf * sf + T(1e-12));
+        f[3 * k + 2] = float(tmin(T(2), tmax(T(-2), r)));
+    }
+    const T uc = Uc.y / hc, vc = Uc.z / hc;
+    const T un = uc * nx + vc * ny, ut = -uc * ny + vc * nx;
+    f[12] = float(tanh(sqrt(un * un + ut * ut) / sqrt(g * tmax(hc, T(1e-6)))));
+    f[13] = float(tanh((Uk.x - hc) / (hc + T(0.01))));
+    return true;
+}
+
+}  // namespace swe

@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libswe.so")
+# SWE_LIBRARY selects another build of the same library (e.g. a variant
+# compiled with different flags for a measurement)
+LIB_PATH = os.environ.get("SWE_LIBRARY", os.path.join(HERE, "libswe.so"))
 
 SWE_ABI_VERSION = 1
 SWE_OK = 0
@@ -30,6 +32,8 @@ WAF_SUPERBEE, WAF_GODUNOV, WAF_UNLIMITED = 0, 1, 2
 HOST, DEVICE = 0, 1
 BC_WALL, BC_TRANSMISSIVE, BC_INFLOW, BC_OUTFLOW, BC_HALO = -1, -2, -3, -4, -5
 HEALTH_NONFINITE, HEALTH_NEGDEPTH, HEALTH_CLIPPED = 1, 2, 4
+MLP_NPARAM = 1569
+PAIR_RECORD = 32
 
 
 class SweError(RuntimeError):
@@ -40,6 +44,13 @@ class SweError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libswe.so not built ({LIB_PATH}); run python paper_2307_16758_amd/build.py")
+# torch ships its own HIP runtime.  Loading it first makes libswe.so bind to
+# that same runtime (same soname); loading libswe.so first would put two HIP
+# runtimes in the process and torch would then see no GPU.
+try:
+    import torch  # noqa: F401
+except ImportError:  # torch is optional: host toolkit and host buffers need no torch
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 i32p = C.POINTER(C.c_int32)
@@ -88,6 +99,11 @@ _sig("swe_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
                                 C.c_double])
 _sig("swe_read_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int])
 _sig("swe_step", C.c_int, [C.c_void_p, C.c_int, C.c_double])
+_sig("swe_mesh_upload_batch", C.c_int, [C.c_void_p, C.c_int, C.POINTER(swe_mesh)])
+_sig("swe_set_bc_series_scenario", C.c_int, [C.c_void_p, C.c_int, C.c_int, f64p, f64p])
+_sig("swe_batch_offsets", C.c_int, [C.c_void_p, i32p, i32p])
+_sig("swe_scenario_times", C.c_int, [C.c_void_p, f64p])
+_sig("swe_autotune", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _sig("swe_sync", C.c_int, [C.c_void_p])
 _sig("swe_time", C.c_int, [C.c_void_p, f64p])
 _sig("swe_local_dt", C.c_int, [C.c_void_p, f64p])
@@ -96,6 +112,17 @@ _sig("swe_pack_ghosts", C.c_int, [C.c_void_p, C.c_void_p])
 _sig("swe_unpack_ghosts", C.c_int, [C.c_void_p, C.c_void_p])
 _sig("swe_ghost_sizes", C.c_int, [C.c_void_p, i32p, i32p])
 _sig("swe_last_step_ms", C.c_int, [C.c_void_p, C.POINTER(C.c_float)])
+_sig("swe_limiter_set_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_float)])
+_sig("swe_limiter_phi", C.c_int, [C.c_void_p, C.c_void_p])
+_sig("swe_limiter_pairs", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("swe_trainer_create", C.c_int, [C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_void_p)])
+_sig("swe_trainer_destroy", None, [C.c_void_p])
+_sig("swe_trainer_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                        C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                        C.POINTER(C.c_float)])
+_sig("swe_trainer_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.POINTER(C.c_float), C.c_float, C.POINTER(C.c_float)])
+_sig("swe_trainer_get_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float)])
 _sig("swe_dual_graph", C.c_int, [C.c_int32, C.c_int32, i32p, i32p])
 _sig("swe_partition_bfs", C.c_int, [C.c_int32, i32p, C.c_int32, i32p])
 _sig("swe_edge_length_sum", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, C.POINTER(C.c_int8),
@@ -109,8 +136,12 @@ _sig("swe_subdomain_free", None, [C.c_void_p])
 
 EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error", "swe_strerror",
             "swe_mesh_upload", "swe_set_bc_series", "swe_set_state", "swe_read_state",
-            "swe_step", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
+            "swe_step", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
+            "swe_batch_offsets", "swe_scenario_times", "swe_autotune", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
             "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
+            "swe_limiter_set_weights", "swe_limiter_phi", "swe_limiter_pairs",
+            "swe_trainer_create", "swe_trainer_destroy", "swe_trainer_loss_grad",
+            "swe_trainer_step", "swe_trainer_get_params",
             "swe_dual_graph", "swe_partition_bfs", "swe_edge_length_sum", "swe_morton_keys", "swe_subdomain_build",
             "swe_subdomain_view_get", "swe_subdomain_free"]
 
@@ -316,6 +347,37 @@ class Solver:
         self._chk(_lib.swe_mesh_upload(self.ctx, C.byref(s)))
         self.mesh = mesh
 
+    def mesh_upload_batch(self, meshes):
+        structs = (swe_mesh * len(meshes))(*[m.c_struct() for m in meshes])
+        self._chk(_lib.swe_mesh_upload_batch(self.ctx, len(meshes), structs))
+        self.meshes = list(meshes)
+        n = C.c_int32()
+        self._chk(_lib.swe_batch_offsets(self.ctx, C.byref(n), None))
+        off = np.empty(n.value + 1, np.int32)
+        self._chk(_lib.swe_batch_offsets(self.ctx, C.byref(n), _i32(off)))
+        self.offsets = off
+        self.mesh = MeshArrays(node_xy=np.zeros((1, 2)), n_owned=int(off[-1]),
+                               cell_nodes=np.zeros((int(off[-1]), 3), np.int32),
+                               cell_gid=np.zeros(0, np.int64), cell_nbr=np.zeros(0, np.int32),
+                               cell_b=np.zeros(0), cell_manning=np.zeros(0),
+                               peers=np.zeros(0, np.int32), recv_off=np.zeros(1, np.int32),
+                               send_off=np.zeros(1, np.int32), send_idx=np.zeros(0, np.int32))
+
+    def set_bc_series_scenario(self, scen, t, q):
+        t = np.ascontiguousarray(t, np.float64)
+        q = np.ascontiguousarray(q, np.float64)
+        self._chk(_lib.swe_set_bc_series_scenario(self.ctx, int(scen), t.shape[0], _f64(t), _f64(q)))
+
+    def scenario_times(self):
+        out = np.empty(len(self.offsets) - 1, np.float64)
+        self._chk(_lib.swe_scenario_times(self.ctx, _f64(out)))
+        return out
+
+    def autotune(self, n_steps=10):
+        b, g = C.c_int(), C.c_int()
+        self._chk(_lib.swe_autotune(self.ctx, int(n_steps), C.byref(b), C.byref(g)))
+        return b.value, g.value
+
     def set_bc_series(self, t, q):
         t = np.ascontiguousarray(t, np.float64)
         q = np.ascontiguousarray(q, np.float64)
@@ -376,3 +438,70 @@ class Solver:
         f = C.c_float()
         self._chk(_lib.swe_last_step_ms(self.ctx, C.byref(f)))
         return f.value
+
+    # ---------------------------------------------------- learned limiter
+    def limiter_set_weights(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.shape == (MLP_NPARAM,)
+        self._chk(_lib.swe_limiter_set_weights(self.ctx, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def limiter_phi(self, out):
+        """phi of every half-edge into a float32 CUDA tensor of 3*n_total."""
+        self._chk(_lib.swe_limiter_phi(self.ctx, C.c_void_p(out.data_ptr())))
+
+    def limiter_pairs(self, fine: "Solver", children, out):
+        """children: int32 CUDA tensor [4*n_total]; out: float32 CUDA tensor
+        [3*n_total*32]."""
+        self._chk(_lib.swe_limiter_pairs(self.ctx, fine.ctx, C.c_void_p(children.data_ptr()),
+                                         C.c_void_p(out.data_ptr())))
+
+
+class Trainer:
+    """FP32 Adam trainer of the limiter network (device kernels)."""
+
+    def __init__(self, init_params, device=0):
+        p = np.ascontiguousarray(init_params, np.float32)
+        assert p.shape == (MLP_NPARAM,)
+        h = C.c_void_p()
+        _check(_lib.swe_trainer_create(device, p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.swe_trainer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def _wv(wv):
+        w = np.ascontiguousarray(wv, np.float32)
+        assert w.shape == (4,)
+        return w
+
+    def loss_grad(self, rec, idx, wv):
+        w = self._wv(wv)
+        loss = C.c_float()
+        g = np.empty(MLP_NPARAM, np.float32)
+        n_rec = rec.numel() // PAIR_RECORD
+        _check(_lib.swe_trainer_loss_grad(self.h, C.c_void_p(rec.data_ptr()), n_rec,
+                                          C.c_void_p(idx.data_ptr()), idx.numel(),
+                                          w.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                          g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def step(self, rec, idx, wv, lr):
+        w = self._wv(wv)
+        loss = C.c_float()
+        n_rec = rec.numel() // PAIR_RECORD
+        _check(_lib.swe_trainer_step(self.h, C.c_void_p(rec.data_ptr()), n_rec,
+                                     C.c_void_p(idx.data_ptr()), idx.numel(),
+                                     w.ctypes.data_as(C.POINTER(C.c_float)), float(lr),
+                                     C.byref(loss)))
+        return loss.value
+
+    def params(self):
+        p = np.empty(MLP_NPARAM, np.float32)
+        _check(_lib.swe_trainer_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float))))
+        return p

@@ -1,0 +1,184 @@
+"""Learned limiter on the GPU against the FP64 oracle: matrix-core (BF16)
+inference of phi, MUSCL steps with the learned limiter, training records
+built from a refined-mesh run, and the trainer's gradient.
+
+Tolerances: BF16 operands carry 8 significant bits, so phi may differ from
+the oracle's by a few BF16 ulps of the activations (the oracle rounds the
+same layer inputs to BF16; the remaining difference is FP32 accumulation and
+BF16 ties decided differently): max 2e-2, mean 2e-3.  The trainer runs in
+FP32: per-tensor gradient error <= 1e-2 relative, cosine >= 0.999.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import make_pair, lib
+from oracle import oracle as O
+from swe_inputs import river_channel, refine_scenario
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def params(seed=0, scale=0.3):
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0.0, scale, O.MLP_NPAR).astype(np.float32)
+    return w
+
+
+def flowing_state(sc, steps=150):
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2)
+    h, hu, hv, t, _ = M.run(p, sc.h, sc.hu, sc.hv, steps)
+    return h, hu, hv
+
+
+def small_river():
+    return river_channel(Lx=2000.0, Ly=400.0, nx=80, ny=16, seed=6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mfma_phi_matches_oracle(prec):
+    import torch
+    sc = small_river()
+    h, hu, hv = flowing_state(sc)
+    sc.h, sc.hu, sc.hv = h, hu, hv
+    w = params()
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=prec, limiter=3)
+    s.limiter_set_weights(w)
+    phi = torch.empty(3 * pr.sub.n_total, dtype=torch.float32, device="cuda")
+    s.limiter_phi(phi)
+    g = phi.cpu().numpy().reshape(-1, 3)
+    l2g = pr.sub.l2g
+    dt = np.float32 if prec == 0 else np.float64
+    par.mlp = bf16_round(w)
+    par.mlp_bf16 = 1
+    inp, ref = O.limiter_inputs(M, par, *(a[l2g].astype(dt).astype(np.float64) for a in (h, hu, hv)))
+    elig = inp[..., 23] == 1.0
+    assert elig.sum() > 1000
+    d = np.abs(g - ref)
+    print("phi max/mean diff", d[elig].max(), d[elig].mean())
+    assert np.all(g[~elig] == 0.5)
+    assert d[elig].max() <= 2e-2 and d[elig].mean() <= 2e-3
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 1e-3)])
+def test_learned_limiter_steps(prec, tol):
+    sc = small_river()
+    h, hu, hv = flowing_state(sc)
+    sc.h, sc.hu, sc.hv = h, hu, hv
+    w = params(1)
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=prec, limiter=3)
+    s.limiter_set_weights(w)
+    l2g = pr.sub.l2g
+    par.limiter = O.LEARNED
+    par.mlp = bf16_round(w)
+    par.mlp_bf16 = 1
+    dt = M.dt(par, h[l2g], hu[l2g], hv[l2g])
+    s.step(50, dt)
+    gst = s.read_state()
+    r = M.run(par, h[l2g], hu[l2g], hv[l2g], 50, dt_fixed=dt)
+    errs = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(gst, r[:3])]
+    print("learned limiter", prec, errs)
+    assert max(errs) <= tol
+
+
+def fine_pair(sc, steps=100):
+    """Coarse and red-refined scenario, the fine one run on the GPU; returns
+    solvers, prepared meshes and the children map (coarse local -> fine local)."""
+    import torch
+    swe, prepare_scenario = lib()
+    fs = refine_scenario(sc)
+    fine, _, _, prf = make_pair(fs, "muscl_minmod_rk2", precision=0)
+    fine.step(steps)
+    coarse, Mc, parc, prc = make_pair(sc, "muscl_minmod_rk2", precision=0)
+    g2l = np.empty(fs.n_cells, np.int64)
+    g2l[prf.sub.l2g] = np.arange(prf.sub.n_total)
+    gid = prc.sub.l2g
+    ch = np.stack([g2l[4 * gid + k] for k in range(4)], 1).astype(np.int32)
+    children = torch.from_numpy(ch.ravel().copy()).cuda()
+    return coarse, fine, prc, prf, ch, children, fs, Mc, parc
+
+
+def test_pairs_records():
+    import torch
+    sc = small_river()
+    coarse, fine, prc, prf, ch, children, fs, Mc, parc = fine_pair(sc)
+    n = prc.sub.n_total
+    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    coarse.limiter_pairs(fine, children, rec)
+    R = rec.cpu().numpy().reshape(n, 3, 32)
+    fh, fhu, fhv = fine.read_state()
+    ch_h, ch_hu, ch_hv = fh[ch].astype(np.float64), fhu[ch].astype(np.float64), fhv[ch].astype(np.float64)
+    # restriction is the coarse state now
+    h, hu, hv = coarse.read_state()
+    np.testing.assert_allclose(h, ch_h.mean(1), rtol=1e-6, atol=1e-6)
+    inp, _ = O.limiter_inputs(Mc, parc, h.astype(np.float64), hu.astype(np.float64), hv.astype(np.float64))
+    elig = inp[..., 23] == 1.0
+    ok = R[..., 27] == 1.0
+    assert ok.sum() > 1000 and np.all(elig[ok])
+    np.testing.assert_allclose(R[..., 14:18][ok], inp[..., 14:18][ok], rtol=1e-4, atol=1e-5)
+    np.testing.assert_allclose(R[..., 18:22][ok], inp[..., 18:22][ok], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(R[..., 22], inp[..., 22], rtol=1e-6)
+    assert np.abs(R[..., :14][ok] - inp[..., :14][ok]).max() < 1e-3
+    # target depth: mean of the two children touching the edge
+    for m in range(3):
+        tgt = 0.5 * (ch_h[:, m] + ch_h[:, (m + 1) % 3])
+        np.testing.assert_allclose(R[:, m, 23], tgt, rtol=1e-6, atol=1e-6)
+
+
+def test_trainer_gradient_matches_oracle():
+    import torch
+    swe, _ = lib()
+    sc = small_river()
+    coarse, fine, prc, prf, ch, children, *_ = fine_pair(sc)
+    n = prc.sub.n_total
+    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    coarse.limiter_pairs(fine, children, rec)
+    R = rec.cpu().numpy().reshape(-1, 32)
+    valid = np.where(R[:, 27] == 1.0)[0].astype(np.int32)
+    assert valid.size > 1000
+    idx = torch.from_numpy(valid).cuda()
+    w = params(3, scale=0.2)
+    wv = np.array([1.0, 1.0, 0.5, 0.5], np.float32)
+    tr = swe.Trainer(w)
+    loss, g = tr.loss_grad(rec, idx, wv)
+    V = R[valid].astype(np.float64)
+    lo, go = O.mlp_loss_grad(w.astype(np.float64), V[:, :14], V[:, 14:18], V[:, 18:22], V[:, 22],
+                             V[:, 23:27], wv.astype(np.float64))
+    assert loss == pytest.approx(lo, rel=1e-3)
+    sizes = [32 * 14, 32, 32 * 32, 32, 32, 1]
+    off = 0
+    for sz in sizes:
+        a, b = g[off:off + sz].astype(np.float64), go[off:off + sz]
+        off += sz
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            continue
+        assert np.linalg.norm(a - b) <= 1e-2 * nb
+        assert a @ b / (np.linalg.norm(a) * nb) >= 0.999
+
+
+def test_training_reduces_loss():
+    import torch
+    swe, _ = lib()
+    sc = small_river()
+    coarse, fine, prc, prf, ch, children, *_ = fine_pair(sc, steps=200)
+    n = prc.sub.n_total
+    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    coarse.limiter_pairs(fine, children, rec)
+    R = rec.view(-1, 32)
+    valid = torch.nonzero(R[:, 27] == 1.0).flatten().to(torch.int32)
+    tr = swe.Trainer(params(4, scale=0.1))
+    wv = np.array([1.0, 1.0, 1.0, 1.0], np.float32)
+    l0 = tr.loss_grad(rec, valid, wv)[0]
+    for _ in range(300):
+        tr.step(rec, valid, wv, 3e-3)
+    l1 = tr.loss_grad(rec, valid, wv)[0]
+    print("loss", l0, "->", l1)
+    assert l1 < 0.9 * l0

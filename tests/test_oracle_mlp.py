@@ -1,0 +1,113 @@
+"""Pins of the oracle's learned-limiter network (FP64): analytic gradients
+against central finite differences, output range, the sigmoid's fixed
+points, and the limiter's reductions inside a MUSCL step (phi = 0 is the
+zero-slope scheme bitwise; a NaN network falls back to minmod)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from swe_inputs import river_channel
+
+
+def random_params(seed=0, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, O.MLP_NPAR)
+
+
+def random_batch(n=40, seed=1):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.5, 1.5, (n, O.MLP_IN))
+    q = rng.normal(size=(n, 4))
+    s = rng.normal(size=(n, 4))
+    d = rng.uniform(0.5, 2.0, n)
+    t = q + rng.normal(scale=0.3, size=(n, 4))
+    return x, q, s, d, t
+
+
+def test_gradient_matches_finite_differences():
+    w = random_params()
+    x, q, s, d, t = random_batch()
+    wv = np.array([1.0, 0.5, 2.0, 0.7])
+    loss, g = O.mlp_loss_grad(w, x, q, s, d, t, wv)
+    h = 1e-6
+    fd = np.empty_like(w)
+    for i in range(w.size):
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd[i] = (O.mlp_loss_grad(wp, x, q, s, d, t, wv)[0] - O.mlp_loss_grad(wm, x, q, s, d, t, wv)[0]) / (2 * h)
+    scale = np.abs(fd).max()
+    assert np.abs(g - fd).max() <= 1e-6 * scale
+    assert loss > 0
+
+
+def test_output_range_and_fixed_points():
+    w = random_params(2, scale=2.0)
+    x, *_ = random_batch(200, 3)
+    phi = O.mlp_forward(w, x)
+    assert np.all((phi >= 0) & (phi <= 1))
+    w0 = np.zeros(O.MLP_NPAR)
+    assert np.all(O.mlp_forward(w0, x) == 0.5)
+    w0[-1] = -1e3            # output bias: sigmoid saturates at 0
+    assert np.all(O.mlp_forward(w0, x) == 0.0)
+    # bf16 inputs move phi by at most a few bf16 ulps of the activations
+    pb = O.mlp_forward(w, x, bf16_inputs=True)
+    assert np.abs(pb - phi).max() < 3e-2
+
+
+def _river():
+    return river_channel(Lx=2000.0, Ly=400.0, nx=40, ny=8, seed=4)
+
+
+def _flowing(sc):
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2)
+    h, hu, hv, t, _ = M.run(p, sc.h, sc.hu, sc.hv, 150)
+    return M, h, hu, hv
+
+
+def test_phi_zero_is_zero_slope_bitwise():
+    sc = _river()
+    M, h, hu, hv = _flowing(sc)
+    w = np.zeros(O.MLP_NPAR)
+    w[-1] = -1e3
+    pl = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED, mlp=w)
+    pz = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.ZEROSLOPE)
+    a = M.run(pl, h, hu, hv, 20)
+    b = M.run(pz, h, hu, hv, 20)
+    for i in range(3):
+        assert np.array_equal(a[i], b[i])
+
+
+def test_nan_network_falls_back_to_minmod():
+    sc = _river()
+    M, h, hu, hv = _flowing(sc)
+    w = np.full(O.MLP_NPAR, np.nan)
+    pl = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED, mlp=w)
+    pm = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.MINMOD)
+    a = M.run(pl, h, hu, hv, 20)
+    b = M.run(pm, h, hu, hv, 20)
+    for i in range(3):
+        assert np.array_equal(a[i], b[i])
+
+
+def test_limiter_inputs_consistent_with_reconstruction():
+    """phi = 1 reproduces the central-slope interface values that the
+    limiter-input dump reports (q + d_mid * s), on every eligible half-edge."""
+    sc = _river()
+    M, h, hu, hv = _flowing(sc)
+    w = np.zeros(O.MLP_NPAR)
+    w[-1] = 1e3               # phi = 1
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED, mlp=w)
+    inp, phi = O.limiter_inputs(M, p, h, hu, hv)
+    rh, rb, run, rut, sec = M.interfaces(p, h, hu, hv)
+    elig = inp[..., 23] == 1.0
+    assert elig.sum() > 100
+    assert np.all(phi[elig] == 1.0) and np.all(phi[~elig] == 0.5)
+    rec = inp[..., 14:18] + inp[..., 22:23] * inp[..., 18:22]
+    ok = elig & (rec[..., 0] >= 0)
+    np.testing.assert_allclose(rh[ok], rec[..., 0][ok], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(rb[ok] + rh[ok], rec[..., 1][ok], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(run[ok], rec[..., 2][ok], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(rut[ok], rec[..., 3][ok], rtol=1e-12, atol=1e-12)
+    assert np.all(np.abs(inp[..., :12][elig][:, 0::3]) <= 1.0)
