@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -38,14 +40,24 @@ BYTES_STAGE2 = 114
 BYTES_EULER_F64 = 132   # first-order HLLC, FP64, stored geometry
 
 
+MUSCL_RK2 = dict(precision=0, scheme=1, integrator=1, limiter=0)
+
+
 def workload(name):
-    from swe_inputs import config1, config2, config3
+    """(scenario or list of scenarios, solver options, parts P, ghost layers k)."""
+    from swe_inputs import config1, config2, config3, ensemble_scenarios
     if name == "config1":
-        return config1(), dict(precision=1, scheme=0, integrator=0, limiter=0)
+        return config1(), dict(precision=1, scheme=0, integrator=0, limiter=0), 1, 0
     if name == "config2":
-        return config2(), dict(precision=0, scheme=1, integrator=1, limiter=0)
+        return config2(), MUSCL_RK2, 1, 0
     if name == "config3_full":
-        return config3(), dict(precision=0, scheme=1, integrator=1, limiter=0)
+        return config3(), MUSCL_RK2, 1, 0
+    if name == "config3_part":
+        # one GPU's share: the largest of 32 greedy-BFS parts, 4 ghost layers
+        # (one MUSCL-RK2 step per exchange), send buffers packed every step
+        return config3(), MUSCL_RK2, 32, 4
+    if name == "config5":
+        return ensemble_scenarios(), MUSCL_RK2, 1, 0
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -78,7 +90,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cell-kernel", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the path measured is one GPU's "
               "sub-domain (multi-GPU exchange is not part of this build)", file=sys.stderr)
@@ -88,25 +115,57 @@ def main():
     from paper_2307_16758_amd import swe
     from paper_2307_16758_amd.problem import prepare_scenario
 
-    sc, kw = workload(args.workload)
-    pr = prepare_scenario(sc)
-    s = swe.Solver(device=0, block=args.block, **kw)
-    s.mesh_upload(pr.mesh)
-    if sc.hydrograph is not None:
-        s.set_bc_series(*sc.hydrograph)
-    l2g = pr.sub.l2g
-    s.set_state(sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
-    n_owned = pr.sub.n_owned
+    sc, kw, P, k = workload(args.workload)
+    s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel, **kw)
+    sendbuf = None
+    if isinstance(sc, list):                      # batched ensemble
+        preps = [prepare_scenario(x) for x in sc]
+        s.mesh_upload_batch([p.mesh for p in preps])
+        for i, x in enumerate(sc):
+            if x.hydrograph is not None:
+                s.set_bc_series_scenario(i, *x.hydrograph)
+        s.set_state(np.concatenate([x.h[p.sub.l2g] for x, p in zip(sc, preps)]),
+                    np.concatenate([x.hu[p.sub.l2g] for x, p in zip(sc, preps)]),
+                    np.concatenate([x.hv[p.sub.l2g] for x, p in zip(sc, preps)]))
+        n_owned = int(sum(p.sub.n_owned for p in preps))
+        name = f"{len(sc)} scenarios"
+    else:
+        if P > 1:
+            from paper_2307_16758_amd import swe as _s
+            nbr = _s.swe_dual_graph(sc.mesh.n_nodes, sc.mesh.tri)
+            part = _s.swe_partition_bfs(nbr, P)
+            p = int(np.argmax(np.bincount(part, minlength=P)))
+            pr = prepare_scenario(sc, P=P, p=p, k=k, nbr_global=nbr, part=part)
+        else:
+            pr = prepare_scenario(sc)
+        s.mesh_upload(pr.mesh)
+        if sc.hydrograph is not None:
+            s.set_bc_series(*sc.hydrograph)
+        l2g = pr.sub.l2g
+        s.set_state(sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+        n_owned = pr.sub.n_owned
+        name = sc.name
+        if P > 1:
+            n_send, _ = s.ghost_sizes()
+            sendbuf = torch.empty(3 * max(1, n_send), dtype=torch.float32, device="cuda")
 
+    tuned = s.autotune(10) if args.autotune else None
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(args.steps)
-    s.sync()
+    if sendbuf is None:
+        s.step(args.steps)
+        s.sync()
+        gpu_ms = s.last_step_ms()       # HIP events around the timed steps, library stream
+    else:
+        gpu_ms = 0.0
+        for _ in range(args.steps):     # one step per exchange interval + on-device pack
+            s.step(1)
+            gpu_ms += s.last_step_ms()
+            s.pack_ghosts(sendbuf)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = s.last_step_ms()           # HIP events around the timed steps, library stream
     health = s.health()
 
     rk2 = kw["integrator"] == 1
@@ -132,9 +191,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if kw["precision"] == 0 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {sc.name}, {n_owned} triangles, "
-                               f"{'MUSCL-HLLC-RK2' if rk2 else 'HLLC-Euler'}",
-                   "cells": n_owned, "parallelism": "single GPU, single domain"},
+        "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
+                               f"{'MUSCL-HLLC-RK2' if rk2 else 'HLLC-Euler'}"
+                               + (f", part of {P} with {k} ghost layers + pack" if P > 1 else ""),
+                   "cells": n_owned, "tuned_launch": tuned,
+                   "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_stage", "avg_launch_us": avg_launch_s * 1e6,
@@ -142,7 +203,8 @@ def main():
         "health_bits": health,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sc[0] if isinstance(sc, list) else sc, kw,
+                                           args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -103,8 +103,10 @@ typedef struct {
     double cfl;        /* default 0.45 */
     double eps;        /* wet/dry threshold [m], default 1e-6 */
     double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
-    int block;         /* threads per block for the cell kernels (0: autotuned/default) */
-    int reserved[7];
+    int block;         /* threads per block = cells per tile: 64, 128 or 256 (0: 256) */
+    int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the
+                          tiled kernel for HLLC1 and MUSCL (WAF always uses the cell kernel) */
+    int reserved[6];
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).
@@ -169,10 +171,12 @@ int swe_set_bc_series_scenario(swe_ctx *ctx, int scenario, int n, const double *
 int swe_batch_offsets(const swe_ctx *ctx, int32_t *n_scenarios, int32_t *offsets);
 int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
 
-/* Autotuner: times n_steps CFL steps for each launch shape (64, 128 or 256
- * threads per block; one tile per block or a persistent grid of
- * 2048 / block blocks per compute unit) from the current state, keeps the
- * fastest and restores the state, clocks and time.  Outputs may be NULL. */
+/* Autotuner: times n_steps CFL steps for each launch shape (tiled or cell
+ * kernel; 64, 128 or 256 threads per block; one tile per block or a
+ * persistent grid of 2048 / block blocks per compute unit) from the current
+ * state, keeps the fastest and restores the state, clocks and time.  The
+ * choice never changes results (every variant computes the same values).
+ * Outputs may be NULL. */
 int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
 
 /* n_steps explicit steps, asynchronous on the context's stream.
@@ -219,7 +223,8 @@ int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
  * set to the restriction (mean of the children) at t = 0, and dev_rec
  * [3*n_total(coarse)][32] receives per half-edge: features[14], cell values
  * (h, eta, u_n, u_t)[4], central slopes[4], d_mid, target[4] = mean of the two
- * children touching the edge, valid flag.  Children out of range give
+ * children touching the edge, valid flag, and the minmod interface values
+ * (h, eta, u_n, u_t)[4] of the same half-edge.  Children out of range give
  * SWE_ERR_ARG. */
 int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_children, float *dev_rec);
 

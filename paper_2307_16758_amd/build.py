@@ -20,6 +20,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              # (about 1 ulp) instead of the correctly rounded sequences; the
              # FP64 path is unaffected
              "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+             # FP32 denormals flushed (depths below eps are dry anyway)
+             "-fgpu-flush-denormals-to-zero",
              "-Wno-unused-result"] + os.environ.get("SWE_EXTRA_HIPFLAGS", "").split()
 
 

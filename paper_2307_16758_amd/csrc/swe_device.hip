@@ -100,10 +100,10 @@ __device__ __forceinline__ void boundary_flux(int tag, const T4 &Uc, T nx, T ny,
         F[0] = T(0); F[1] = T(0.5) * g * h * h; F[2] = T(0);
     } else if (tag == kBcInflow) {
         const T hl = tmax(h, T(1e-3));
-        F[0] = -q_in; F[1] = q_in * q_in / hl + T(0.5) * g * h * h; F[2] = T(0);
+        F[0] = -q_in; F[1] = fdiv(q_in * q_in, hl) + T(0.5) * g * h * h; F[2] = T(0);
     } else if (tag == kBcOutflow) {
         const T hg = tmax(T(0), stage - Uc.w);
-        const T un = h > eps ? U[1] / h : T(0), ut = h > eps ? U[2] / h : T(0);
+        const T un = h > eps ? fdiv(U[1], h) : T(0), ut = h > eps ? fdiv(U[2], h) : T(0);
         T UG[3] = {hg, hg * un, hg * ut};
         flux_hllc(g, eps, U, UG, F);
     } else {
@@ -117,7 +117,7 @@ __device__ __forceinline__ void boundary_flux(int tag, const T4 &Uc, T nx, T ny,
 template <typename T, typename T4>
 __device__ __forceinline__ T tangential(const T4 &U, T nx, T ny, T eps)
 {
-    return U.x > eps ? (-U.y * ny + U.z * nx) / U.x : T(0);
+    return U.x > eps ? fdiv(-U.y * ny + U.z * nx, U.x) : T(0);
 }
 
 // upwind mean of eta and v (L frame) over a cell's two upwind neighbours; a
@@ -244,7 +244,7 @@ __device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
                 const bool hk = waf_upwind(Uka, hka, Ukb, hkb, nLx, nLy, eps, ek, vk);
                 if (isL) { w.eLu = eo; w.vLu = vo; w.hasLu = ho; w.eRu = ek; w.vRu = vk; w.hasRu = hk; }
                 else { w.eLu = ek; w.vLu = vk; w.hasLu = hk; w.eRu = eo; w.vRu = vo; w.hasRu = ho; }
-                flux_waf<T, WAFM>(g, eps, dt / dw.w, UL, UR, w, F);
+                flux_waf<T, WAFM>(g, eps, fdiv(dt, dw.w), UL, UR, w, F);
             } else {
                 flux_hllc(g, eps, UL, UR, F);
             }
@@ -270,9 +270,9 @@ __device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
         if (nh <= eps) {
             nu = T(0); nv = T(0);
         } else if (cg.z > T(0)) {  // Manning, point-implicit
-            const T sp = sqrt(nu * nu + nv * nv) / nh;
-            const T f = T(1) + dt * g * cg.z * sp / (nh * cbrt(nh));
-            nu /= f; nv /= f;
+            const T sp = fdiv(sqrt(nu * nu + nv * nv), nh);
+            const T f = T(1) + dt * g * cg.z * sp * pow_m43(nh);
+            { const T rf = frcp(f); nu *= rf; nv *= rf; }
         }
         if (a.kind == 2) {  // SSP-RK2: average with U^n
             const T4 U0c = a.U0[c];
@@ -287,9 +287,9 @@ __device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
         if (flags) atomicOr(a.health, flags);
         scen = s;
         if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
-            const T u = nu / nh, v = nv / nh;
+            const T u = fdiv(nu, nh), v = fdiv(nv, nh);
             const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-            ratio = double(cg.y / lm);
+            ratio = double(fdiv(cg.y, lm));
             rad = double(cg.y);
             lam = double(lm);
         }
@@ -345,6 +345,283 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
         stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
 }
 
+// ------------------------------------------------------------------------
+// Tiled stage kernel (first-order HLLC and MUSCL-HLLC).  A block owns one
+// tile of TILE consecutive (Morton-ordered) cells:
+//  1. every thread forms the primitive values of its cell and its 1-ring,
+//     reconstructs its three half-edges into LDS, and files its edges as
+//     tasks: an edge to a cell of the same tile is filed once, by the cell
+//     that is the L side of the canonical orientation; an edge to a cell
+//     outside the tile is filed by each side;
+//  2. the block runs the task lists densely (outside edges first: they also
+//     reconstruct the far side from its 2-ring; then inside edges, whose far
+//     side is already in LDS): hydrostatic reconstruction, HLLC in the
+//     canonical orientation, side corrections, results to LDS per half-edge;
+//  3. every thread sums its three half-edges (plus boundary fluxes and the
+//     centred bed term), updates, applies Manning and the cleanup.
+// The flux of an edge is the same function of the same operands wherever it
+// is evaluated, so results do not depend on the tiling (sub-domain runs stay
+// bitwise equal to undecomposed runs) and contributions cancel bitwise.
+template <typename T, bool MUSCL_, int LIM, int TILE>
+__global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
+{
+    using T4 = typename V4<T>::type;
+    __shared__ T4 sP[TILE];
+    __shared__ T4 sR[3 * TILE];
+    __shared__ T sF0[3 * TILE], sF1[3 * TILE], sF2[3 * TILE];
+    __shared__ int4 sNb[TILE];
+    __shared__ int sTask[2][3 * TILE];
+    __shared__ int sCount[2];
+    if (blockIdx.x == 0) {
+        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
+            if (a.kind != 2) {
+                Clock &r = a.clock[3 * s + a.slot_reset];
+                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
+            }
+            if (a.kind != 1) {
+                const Clock cur = a.clock[3 * s + a.slot_cur];
+                a.clock[3 * s + a.slot_next].t =
+                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
+            }
+        }
+    }
+    const T g = a.g, eps = a.eps;
+    const int ntiles = (a.n + TILE - 1) / TILE;
+    for (int tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+        const int c0 = tile * TILE, cl = threadIdx.x, c = c0 + cl;
+        const bool active = c < a.n;
+        if (threadIdx.x < 2) sCount[threadIdx.x] = 0;
+        __syncthreads();
+        // ---- 1: primitives, own half-edges, task lists
+        int4 nb4 = make_int4(-1, -1, -1, 0);
+        T4 Uc;
+        T4 ge[3];
+        if (active) {
+            nb4 = a.nbr[c];
+            Uc = a.Uin[c];
+            const int nb[3] = {nb4.x, nb4.y, nb4.z};
+            const unsigned word = (unsigned)nb4.w;
+            const Prim<T> pc = prim(Uc, eps);
+            Prim<T> pn[3];
+            bool hn[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                hn[m] = nb[m] >= 0;
+                pn[m] = hn[m] ? prim(a.Uin[nb[m]], eps) : pc;
+            }
+            T4 pv;
+            pv.x = pc.h; pv.y = pc.b; pv.z = pc.u; pv.w = pc.v;
+            sP[cl] = pv;
+            sNb[cl] = nb4;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                ge[m] = a.he_geo[3 * c + m];
+                T4 dist;
+                dist.x = T(0); dist.y = T(0); dist.z = T(0); dist.w = T(0);
+                float phi = 0.0f;
+                if (MUSCL_ && hn[m]) {
+                    dist = a.he_dist[3 * c + m];
+                    if (LIM == kLearned) phi = a.phi[3 * c + m];
+                }
+                const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+                const Half<T> r = recon2<T, T4, MUSCL_, LIM>(pc, pn[m], hn[m], pn[ma], hn[ma], pn[mb],
+                                                              hn[mb], ge[m].x, ge[m].y, ge[m].w,
+                                                              dist, phi, eps);
+                T4 rv;
+                rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
+                sR[3 * cl + m] = rv;
+                const int k = nb[m];
+                if (k >= 0) {
+                    const int kl = k - c0;
+                    if (kl >= 0 && kl < TILE) {
+                        if ((word >> (6 + m)) & 1u) sTask[1][atomicAdd(&sCount[1], 1)] = 4 * cl + m;
+                    } else {
+                        sTask[0][atomicAdd(&sCount[0], 1)] = 4 * cl + m;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 2: edge tasks (outside-tile edges, then inside-tile edges)
+#pragma unroll
+        for (int list = 0; list < 2; ++list) {
+            const int nt = sCount[list];
+            for (int i = threadIdx.x; i < nt; i += TILE) {
+                const int task = sTask[list][i];
+                const int tl = task >> 2, m = task & 3, tc = c0 + tl;
+                const int4 tn = sNb[tl];
+                const unsigned word = (unsigned)tn.w;
+                const int k = m == 0 ? tn.x : (m == 1 ? tn.y : tn.z);
+                const int jb = (word >> (2 * m)) & 3;
+                const bool isL = (word >> (6 + m)) & 1u;
+                const T4 gm = a.he_geo[3 * tc + m];
+                const T nx = gm.x, ny = gm.y;
+                const T4 ov = sR[3 * tl + m];
+                T4 kv;
+                int kl = -1;
+                if (list == 1) {
+                    kl = k - c0;
+                    kv = sR[3 * kl + jb];
+                } else {
+                    // far side: its own reconstruction across this edge, from its 2-ring
+                    const T4 Uk = a.Uin[k];
+                    const Prim<T> pk = prim(Uk, eps);
+                    const T4 pcv = sP[tl];
+                    Prim<T> pc;
+                    pc.h = pcv.x; pc.b = pcv.y; pc.u = pcv.z; pc.v = pcv.w;
+                    Prim<T> pka = pk, pkb = pk;
+                    bool hka = false, hkb = false;
+                    T4 dk;
+                    dk.x = T(0); dk.y = T(0); dk.z = T(0); dk.w = T(0);
+                    T dmk = T(0);
+                    float phik = 0.0f;
+                    if (MUSCL_) {
+                        const int4 nk = a.nbr[k];
+                        const int nk3[3] = {nk.x, nk.y, nk.z};
+                        const int ka = nk3[(jb + 1) % 3], kb = nk3[(jb + 2) % 3];
+                        hka = ka >= 0;
+                        hkb = kb >= 0;
+                        if (hka) pka = prim(a.Uin[ka], eps);
+                        if (hkb) pkb = prim(a.Uin[kb], eps);
+                        dk = a.he_dist[3 * k + jb];
+                        dmk = a.he_geo[3 * k + jb].w;
+                        if (LIM == kLearned) phik = a.phi[3 * k + jb];
+                    }
+                    const Half<T> r = recon2<T, T4, MUSCL_, LIM>(pk, pc, true, pka, hka, pkb, hkb, -nx,
+                                                                  -ny, dmk, dk, phik, eps);
+                    kv.x = r.h; kv.y = r.b; kv.z = r.un; kv.w = r.ut;
+                }
+                // hydrostatic reconstruction
+                const T be = tmax(ov.y, kv.y);
+                const T hso = tmax(T(0), ov.x + ov.y - be);
+                const T hsk = tmax(T(0), kv.x + kv.y - be);
+                T F[3];
+                T nLx, nLy;
+                if (isL) {
+                    hllc_prim(g, eps, hso, ov.z, ov.w, hsk, -kv.z, -kv.w, F);
+                    nLx = nx; nLy = ny;
+                } else {
+                    hllc_prim(g, eps, hsk, kv.z, kv.w, hso, -ov.z, -ov.w, F);
+                    nLx = -nx; nLy = -ny;
+                }
+                const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
+                const T sg = isL ? T(1) : T(-1);
+                const T po = T(0.5) * g * (ov.x * ov.x - hso * hso);
+                sF0[3 * tl + m] = sg * G0;
+                sF1[3 * tl + m] = sg * G1 + po * nx;
+                sF2[3 * tl + m] = sg * G2 + po * ny;
+                if (list == 1) {  // the other cell's half-edge (its normal is -n)
+                    const T pk_ = T(0.5) * g * (kv.x * kv.x - hsk * hsk);
+                    sF0[3 * kl + jb] = -(sg * G0);
+                    sF1[3 * kl + jb] = -(sg * G1) - pk_ * nx;
+                    sF2[3 * kl + jb] = -(sg * G2) - pk_ * ny;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3: cell sums, update, friction, cleanup, CFL
+        double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
+        int scen = -1;
+        if (active) {
+            const unsigned word = (unsigned)nb4.w;
+            const int s = (int)(word >> kScenShift);
+            const Clock ck = a.clock[3 * s + a.slot_cur];
+            const double dtd = step_dt(ck, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
+            const T dt = T(dtd);
+            const T4 cg = a.cell[c];
+            const int nb[3] = {nb4.x, nb4.y, nb4.z};
+            T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const T nx = ge[m].x, ny = ge[m].y, L = ge[m].z;
+                if (nb[m] < 0) {
+                    const ScenParams sp = a.scen[s];
+                    const double t_st = ck.t + (a.kind == 2 ? dtd : 0.0);
+                    const T q_in = nb[m] == kBcInflow
+                                       ? T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len)
+                                       : T(0);
+                    T G[3];
+                    boundary_flux<T, T4>(nb[m], Uc, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
+                    acc0 += L * G[0];
+                    acc1 += L * G[1];
+                    acc2 += L * G[2];
+                } else {
+                    const T4 rv = sR[3 * cl + m];
+                    const T sb = T(0.5) * g * (rv.x + Uc.x) * (rv.y - Uc.w);  // centred bed term
+                    acc0 += L * sF0[3 * cl + m];
+                    acc1 += L * (sF1[3 * cl + m] + sb * nx);
+                    acc2 += L * (sF2[3 * cl + m] + sb * ny);
+                }
+            }
+            T nh = Uc.x - dt * (acc0 * cg.x);
+            T nu = Uc.y - dt * (acc1 * cg.x);
+            T nv = Uc.z - dt * (acc2 * cg.x);
+            int flags = 0;
+            if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
+            if (nh < T(0)) {
+                flags |= nh < -eps ? kHealthNegDepth : kHealthClipped;
+                nh = T(0);
+            }
+            if (nh <= eps) {
+                nu = T(0); nv = T(0);
+            } else if (cg.z > T(0)) {  // Manning, point-implicit
+                const T sp = sqrt(nu * nu + nv * nv) * frcp(nh);
+                const T f = T(1) + dt * g * cg.z * sp * pow_m43(nh);
+                const T rf = frcp(f);
+                nu *= rf; nv *= rf;
+            }
+            if (a.kind == 2) {
+                const T4 U0c = a.U0[c];
+                nh = T(0.5) * (U0c.x + nh);
+                nu = T(0.5) * (U0c.y + nu);
+                nv = T(0.5) * (U0c.z + nv);
+                if (nh <= eps) { nu = T(0); nv = T(0); }
+            }
+            T4 out;
+            out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
+            a.Uout[c] = out;
+            if (flags) atomicOr(a.health, flags);
+            scen = s;
+            if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
+                const T r = frcp(nh);
+                const T u = nu * r, v = nv * r;
+                const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
+                ratio = double(fdiv(cg.y, lm));
+                rad = double(cg.y);
+                lam = double(lm);
+            }
+        }
+        if (a.kind != 1) {
+            int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
+            for (int o = 32; o > 0; o >>= 1) {
+                smin = min(smin, __shfl_xor(smin, o));
+                smax = max(smax, __shfl_xor(smax, o));
+            }
+            if (smax >= 0) {
+                if (smin == smax) {
+                    for (int o = 32; o > 0; o >>= 1) {
+                        ratio = fmin(ratio, __shfl_xor(ratio, o));
+                        rad = fmin(rad, __shfl_xor(rad, o));
+                        lam = fmax(lam, __shfl_xor(lam, o));
+                    }
+                    if ((threadIdx.x & 63) == 0 && lam > 0.0) {
+                        Clock &nx = a.clock[3 * smin + a.slot_next];
+                        atomicMin(&nx.ratio_min, dbits(ratio));
+                        atomicMin(&nx.rad_min, dbits(rad));
+                        atomicMax(&nx.lam_max, dbits(lam));
+                    }
+                } else if (scen >= 0 && lam > 0.0) {
+                    Clock &nx = a.clock[3 * scen + a.slot_next];
+                    atomicMin(&nx.ratio_min, dbits(ratio));
+                    atomicMin(&nx.rad_min, dbits(rad));
+                    atomicMax(&nx.lam_max, dbits(lam));
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
 // CFL minima of the current state into one clock slot (after set_state):
 // wave-wide reduction, one set of atomics per wave and scenario.
 template <typename T>
@@ -358,9 +635,9 @@ __global__ void k_cfl_init(int n, const int4 *nbr, const typename V4<T>::type *c
         const unsigned word = (unsigned)nbr[c].w;
         const T h = U[c].x;
         if (((word >> kOwnedBit) & 1u) && h > eps) {
-            const T u = U[c].y / h, v = U[c].z / h;
+            const T u = fdiv(U[c].y, h), v = fdiv(U[c].z, h);
             const T lm = sqrt(u * u + v * v) + sqrt(g * h);
-            ratio = double(cell[c].y / lm);
+            ratio = double(fdiv(cell[c].y, lm));
             rad = double(cell[c].y);
             lam = double(lm);
         }
@@ -550,7 +827,33 @@ int push_scenarios(swe_ctx *c)
 
 template <typename T> using KernelFn = void (*)(StageArgs<T>);
 
-template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm)
+template <typename T, int TILE> KernelFn<T> pick_tiled(int scheme, int lim)
+{
+    if (scheme == kHLLC1) return k_stage_tiled<T, false, kMinmod, TILE>;
+    switch (lim) {
+    case kSuperbee: return k_stage_tiled<T, true, kSuperbee, TILE>;
+    case kVanAlbada: return k_stage_tiled<T, true, kVanAlbada, TILE>;
+    case kLearned: return k_stage_tiled<T, true, kLearned, TILE>;
+    case kZeroSlope: return k_stage_tiled<T, true, kZeroSlope, TILE>;
+    default: return k_stage_tiled<T, true, kMinmod, TILE>;
+    }
+}
+
+template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm);
+
+// Stage kernel of a configuration: the tiled kernel for first-order HLLC and
+// MUSCL (tile = block size 64, 128 or 256), the cell kernel for WAF.
+template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int block, int cell)
+{
+    if (scheme != kWAF && !cell) {
+        if (block == 64) return pick_tiled<T, 64>(scheme, lim);
+        if (block == 128) return pick_tiled<T, 128>(scheme, lim);
+        return pick_tiled<T, 256>(scheme, lim);
+    }
+    return pick_cell_kernel<T>(scheme, lim, wafm);
+}
+
+template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm)
 {
     if (scheme == kHLLC1) return k_stage<T, kHLLC1, kMinmod, 0>;
     if (scheme == kWAF) {
@@ -593,7 +896,8 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.slot_cur = (int)(step % 3);
     a.slot_next = (int)((step + 1) % 3);
     a.slot_reset = (int)((step + 2) % 3);
-    KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter);
+    KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, c->block,
+                                   c->cfg.cell_kernel);
     const int B = c->block;
     const int ntiles = (c->n_total + B - 1) / B;
     const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
@@ -679,7 +983,8 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
-        !(cfg->eps >= 0) || (cfg->block != 0 && (cfg->block % 64 || cfg->block > 256 || cfg->block < 64)))
+        !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) ||
+        cfg->cell_kernel < 0 || cfg->cell_kernel > 1)
         return SWE_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_ERR_DEVICE;
@@ -1048,8 +1353,12 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     float best = 1e30f;
     int best_b = c->block, best_g = c->grid_persist;
     int rc = SWE_OK;
+    const int cell0 = c->cfg.cell_kernel;
+    int best_cell = cell0;
+    for (int cellk = 0; cellk < (c->cfg.scheme == SWE_WAF ? 1 : 2); ++cellk)
     for (int B : {64, 128, 256}) {
         for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
+            c->cfg.cell_kernel = c->cfg.scheme == SWE_WAF ? cell0 : cellk;
             c->block = B;
             c->grid_persist = persist ? ncu * (2048 / B) : 0;
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -1061,12 +1370,15 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
             if (rc != SWE_OK) break;
             float ms = 0.f;
             rc = swe_last_step_ms(c, &ms);
-            if (rc == SWE_OK && ms < best) { best = ms; best_b = B; best_g = c->grid_persist; }
+            if (rc == SWE_OK && ms < best) {
+                best = ms; best_b = B; best_g = c->grid_persist; best_cell = c->cfg.cell_kernel;
+            }
         }
     }
     c->use_graphs = graphs;
     c->block = best_b;
     c->grid_persist = best_g;
+    c->cfg.cell_kernel = best_cell;
     (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->clock, saveK, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);

@@ -39,6 +39,21 @@ struct ScenParams {
 
 template <typename T> struct Half { T h, b, un, ut; };
 
+// Division in the working precision: FP32 through the hardware reciprocal
+// (1 ulp; denormals are flushed in this build), FP64 exact.
+template <typename T> __device__ __forceinline__ T frcp(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T> __device__ __forceinline__ T fdiv(T a, T b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// h^(-4/3) of the Manning term: FP32 as 2^(-4/3 log2 h) on the hardware
+// log2 / exp2 (about 1e-6 relative), FP64 through cbrt.
+template <typename T> __device__ __forceinline__ T pow_m43(T h) { return T(1) / (h * cbrt(h)); }
+template <> __device__ __forceinline__ float pow_m43<float>(float h)
+{
+    return __builtin_amdgcn_exp2f(-1.3333333f * __builtin_amdgcn_logf(h));
+}
+
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 
@@ -46,8 +61,8 @@ template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b
 template <typename T, typename T4>
 __device__ __forceinline__ void frame_vel(const T4 &U, T nx, T ny, T eps, T &un, T &ut)
 {
-    const T u = U.x > eps ? U.y / U.x : T(0);
-    const T v = U.x > eps ? U.z / U.x : T(0);
+    const T u = U.x > eps ? fdiv(U.y, U.x) : T(0);
+    const T v = U.x > eps ? fdiv(U.z, U.x) : T(0);
     un = u * nx + v * ny;
     ut = -u * ny + v * nx;
 }
@@ -57,7 +72,7 @@ __device__ __forceinline__ void frame_vel(const T4 &U, T nx, T ny, T eps, T &un,
 template <typename T, int LIM>
 __device__ __forceinline__ T limit(T sb, T sf)
 {
-    if (LIM == kVanAlbada) return sb * sf > T(0) ? sb * sf * (sb + sf) / (sb * sb + sf * sf) : T(0);
+    if (LIM == kVanAlbada) return sb * sf > T(0) ? fdiv(sb * sf * (sb + sf), sb * sb + sf * sf) : T(0);
     if (LIM == kZeroSlope) return T(0);
     const T beta = LIM == kSuperbee ? T(2) : T(1);
     if (sf > T(0)) return tmax(T(0), tmax(tmin(beta * sb, sf), tmin(sb, beta * sf)));
@@ -139,8 +154,8 @@ __device__ __forceinline__ void wave_fan(T g, T eps, const T UL[3], const T UR[3
     W.hL = UL[0]; W.hR = UR[0];
     W.dry = (W.hL <= eps && W.hR <= eps);
     const bool wl = W.hL > eps, wr = W.hR > eps;
-    W.uL = wl ? UL[1] / W.hL : T(0); W.vL = wl ? UL[2] / W.hL : T(0);
-    W.uR = wr ? UR[1] / W.hR : T(0); W.vR = wr ? UR[2] / W.hR : T(0);
+    W.uL = wl ? fdiv(UL[1], W.hL) : T(0); W.vL = wl ? fdiv(UL[2], W.hL) : T(0);
+    W.uR = wr ? fdiv(UR[1], W.hR) : T(0); W.vR = wr ? fdiv(UR[2], W.hR) : T(0);
     W.qL = wl ? UL[1] : T(0); W.qR = wr ? UR[1] : T(0);
     if (W.dry) return;
     const T hL = W.hL, hR = W.hR, uL = W.uL, uR = W.uR;
@@ -150,28 +165,28 @@ __device__ __forceinline__ void wave_fan(T g, T eps, const T UL[3], const T UR[3
     } else if (!wl) {
         W.SL = uR - T(2) * aR; W.SR = uR + aR; W.Ss = W.SL;
     } else {
-        const T h0 = T(0.5) * (hL + hR) - T(0.25) * (uR - uL) * (hL + hR) / (aR + aL);
+        const T h0 = T(0.5) * (hL + hR) - fdiv(T(0.25) * (uR - uL) * (hL + hR), aR + aL);
         T hs;
         if (h0 <= tmin(hL, hR)) {
             const T t = T(0.5) * (aR + aL) + T(0.25) * (uL - uR);
-            hs = t > T(0) ? t * t / g : T(0);
+            hs = t > T(0) ? fdiv(t * t, g) : T(0);
         } else {
-            const T gL = sqrt(g * (h0 + hL) / (T(2) * h0 * hL));
-            const T gR = sqrt(g * (h0 + hR) / (T(2) * h0 * hR));
-            hs = (hL * gL + hR * gR + uL - uR) / (gL + gR);
+            const T gL = sqrt(fdiv(g * (h0 + hL), T(2) * h0 * hL));
+            const T gR = sqrt(fdiv(g * (h0 + hR), T(2) * h0 * hR));
+            hs = fdiv(hL * gL + hR * gR + uL - uR, gL + gR);
         }
-        const T pL = hs > hL ? sqrt((hs + hL) * hs / (T(2) * hL * hL)) : T(1);
-        const T pR = hs > hR ? sqrt((hs + hR) * hs / (T(2) * hR * hR)) : T(1);
+        const T pL = hs > hL ? sqrt(fdiv((hs + hL) * hs, T(2) * hL * hL)) : T(1);
+        const T pR = hs > hR ? sqrt(fdiv((hs + hR) * hs, T(2) * hR * hR)) : T(1);
         W.SL = uL - aL * pL;
         W.SR = uR + aR * pR;
-        W.Ss = (W.SL * hR * (uR - W.SR) - W.SR * hL * (uL - W.SL)) /
-               (hR * (uR - W.SR) - hL * (uL - W.SL));
+        W.Ss = fdiv(W.SL * hR * (uR - W.SR) - W.SR * hL * (uL - W.SL),
+                    hR * (uR - W.SR) - hL * (uL - W.SL));
     }
     W.GL[0] = W.qL; W.GL[1] = W.qL * uL + T(0.5) * g * hL * hL; W.GL[2] = W.qL * W.vL;
     W.GR[0] = W.qR; W.GR[1] = W.qR * uR + T(0.5) * g * hR * hR; W.GR[2] = W.qR * W.vR;
     const T d = W.SR - W.SL;
-    W.Fs[0] = (W.SR * W.GL[0] - W.SL * W.GR[0] + W.SR * W.SL * (hR - hL)) / d;
-    W.Fs[1] = (W.SR * W.GL[1] - W.SL * W.GR[1] + W.SR * W.SL * (W.qR - W.qL)) / d;
+    W.Fs[0] = fdiv(W.SR * W.GL[0] - W.SL * W.GR[0] + W.SR * W.SL * (hR - hL), d);
+    W.Fs[1] = fdiv(W.SR * W.GL[1] - W.SL * W.GR[1] + W.SR * W.SL * (W.qR - W.qL), d);
 }
 
 template <typename T>
@@ -210,8 +225,8 @@ __device__ __forceinline__ T waf_ratio(T S, T qL, T qR, T qLu, T qRu, bool hasLu
 {
     const T dloc = qR - qL;
     if (dloc == T(0)) return T(0);
-    if (S >= T(0)) return hasLu ? (qL - qLu) / dloc : T(0);
-    return hasRu ? (qRu - qR) / dloc : T(0);
+    if (S >= T(0)) return hasLu ? fdiv(qL - qLu, dloc) : T(0);
+    return hasRu ? fdiv(qRu - qR, dloc) : T(0);
 }
 
 template <typename T, int MODE> __device__ __forceinline__ T waf_A(T r, T c)
@@ -301,6 +316,146 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
     f[12] = float(tanh(sqrt(un * un + ut * ut) / sqrt(g * tmax(hc, T(1e-6)))));
     f[13] = float(tanh((Uk.x - hc) / (hc + T(0.01))));
     return true;
+}
+
+}  // namespace swe
+
+// ------------------------------------------------------------------------
+// Primitive-variable forms used by the tiled stage kernel: velocities are
+// formed once per cell (u = hu/h, zero where dry) and the Riemann solver
+// takes (h, u_n, u_t) directly, so no discharge is divided by a depth twice.
+// FP32 uses the hardware reciprocal (1 ulp); FP64 divides exactly.
+namespace swe {
+
+
+template <typename T> struct Prim { T h, b, u, v; };
+
+template <typename T, typename T4>
+__device__ __forceinline__ Prim<T> prim(const T4 &U, T eps)
+{
+    Prim<T> p;
+    p.h = U.x;
+    p.b = U.w;
+    const T r = U.x > eps ? frcp(U.x) : T(0);
+    p.u = U.y * r;
+    p.v = U.z * r;
+    return p;
+}
+
+// beta limiters in branch-free form: zero unless both slopes have the same
+// sign, else the signed max(min(beta|sb|, |sf|), min(|sb|, beta|sf|)); this is
+// the printed MINBEE/SUPERBEE form of Sec. 6.2.3 value for value.
+template <typename T, int LIM>
+__device__ __forceinline__ T limit2(T sb, T sf)
+{
+    if (LIM == kVanAlbada) {
+        const T p = sb * sf;
+        return p > T(0) ? p * (sb + sf) * frcp(sb * sb + sf * sf) : T(0);
+    }
+    if (LIM == kZeroSlope) return T(0);
+    const bool same = (sb > T(0) && sf > T(0)) || (sb < T(0) && sf < T(0));
+    const T ab = sb < T(0) ? -sb : sb, af = sf < T(0) ? -sf : sf;
+    T m;
+    if (LIM == kSuperbee) m = tmax(tmin(T(2) * ab, af), tmin(ab, T(2) * af));
+    else m = tmin(ab, af);
+    return same ? (sf < T(0) ? -m : m) : T(0);
+}
+
+// Interface values of cell C across the edge with outward normal n (Sec.
+// 6.2.3 on the rotated states): K across the edge, A and B the upwind cells.
+template <typename T, typename T4, bool MUSCL_, int LIM>
+__device__ __forceinline__ Half<T> recon2(const Prim<T> &C, const Prim<T> &K, bool hk,
+                                          const Prim<T> &A, bool ha, const Prim<T> &B, bool hb,
+                                          T nx, T ny, T dm, const T4 &dist, float phi, T eps)
+{
+    Half<T> r;
+    r.h = C.h;
+    r.b = C.b;
+    r.un = C.u * nx + C.v * ny;
+    r.ut = -C.u * ny + C.v * nx;
+    if (!MUSCL_) return r;
+    if (!hk || !(C.h > eps) || !(K.h > eps)) return r;
+    if ((ha && !(A.h > eps)) || (hb && !(B.h > eps)) || (!ha && !hb)) return r;
+    const T qc[4] = {C.h, C.h + C.b, r.un, r.ut};
+    const T qk[4] = {K.h, K.h + K.b, K.u * nx + K.v * ny, -K.u * ny + K.v * nx};
+    T qu[4];
+    if (ha && hb) {
+        qu[0] = T(0.5) * (A.h + B.h);
+        qu[1] = T(0.5) * ((A.h + A.b) + (B.h + B.b));
+        qu[2] = T(0.5) * ((A.u * nx + A.v * ny) + (B.u * nx + B.v * ny));
+        qu[3] = T(0.5) * ((-A.u * ny + A.v * nx) + (-B.u * ny + B.v * nx));
+    } else {
+        const Prim<T> &O = ha ? A : B;
+        qu[0] = O.h;
+        qu[1] = O.h + O.b;
+        qu[2] = O.u * nx + O.v * ny;
+        qu[3] = -O.u * ny + O.v * nx;
+    }
+    T out[4];
+    bool done = false;
+    if (LIM == kLearned) {
+        if (phi >= 0.0f && phi <= 1.0f) {
+            const T p = T(phi);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[i] = qc[i] + dm * (p * ((qk[i] - qu[i]) * dist.z));
+            done = out[0] >= T(0);
+        }
+    }
+    if (!done) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T sb = (qc[i] - qu[i]) * dist.x, sf = (qk[i] - qc[i]) * dist.y;
+            out[i] = qc[i] + dm * limit2<T, (LIM == kLearned ? kMinmod : LIM)>(sb, sf);
+        }
+    }
+    if (out[0] < T(0)) return r;
+    r.h = out[0];
+    r.b = out[1] - out[0];
+    r.un = out[2];
+    r.ut = out[3];
+    return r;
+}
+
+// HLLC of Sec. 6.2.1 from depths and normal-frame velocities (the same
+// estimates as wave_fan / flux_hllc).
+template <typename T>
+__device__ __forceinline__ void hllc_prim(T g, T eps, T hL, T uL, T vL, T hR, T uR, T vR, T F[3])
+{
+    const bool wl = hL > eps, wr = hR > eps;
+    if (!wl && !wr) { F[0] = F[1] = F[2] = T(0); return; }
+    if (!wl) { uL = T(0); vL = T(0); }
+    if (!wr) { uR = T(0); vR = T(0); }
+    const T qL = wl ? hL * uL : T(0), qR = wr ? hR * uR : T(0);
+    const T aL = sqrt(g * hL), aR = sqrt(g * hR);
+    T SL, SR, Ss;
+    if (!wr) {
+        SL = uL - aL; SR = uL + T(2) * aL; Ss = SR;
+    } else if (!wl) {
+        SL = uR - T(2) * aR; SR = uR + aR; Ss = SL;
+    } else {
+        const T h0 = T(0.5) * (hL + hR) - T(0.25) * (uR - uL) * (hL + hR) * frcp(aR + aL);
+        T hs;
+        if (h0 <= tmin(hL, hR)) {
+            const T t = T(0.5) * (aR + aL) + T(0.25) * (uL - uR);
+            hs = t > T(0) ? t * t * frcp(g) : T(0);
+        } else {
+            const T gL = sqrt(g * (h0 + hL) * frcp(T(2) * h0 * hL));
+            const T gR = sqrt(g * (h0 + hR) * frcp(T(2) * h0 * hR));
+            hs = (hL * gL + hR * gR + uL - uR) * frcp(gL + gR);
+        }
+        const T pL = hs > hL ? sqrt((hs + hL) * hs * frcp(T(2) * hL * hL)) : T(1);
+        const T pR = hs > hR ? sqrt((hs + hR) * hs * frcp(T(2) * hR * hR)) : T(1);
+        SL = uL - aL * pL;
+        SR = uR + aR * pR;
+        Ss = (SL * hR * (uR - SR) - SR * hL * (uL - SL)) * frcp(hR * (uR - SR) - hL * (uL - SL));
+    }
+    const T GL1 = qL * uL + T(0.5) * g * hL * hL, GR1 = qR * uR + T(0.5) * g * hR * hR;
+    if (SL >= T(0)) { F[0] = qL; F[1] = GL1; F[2] = qL * vL; return; }
+    if (SR <= T(0)) { F[0] = qR; F[1] = GR1; F[2] = qR * vR; return; }
+    const T inv = frcp(SR - SL);
+    F[0] = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
+    F[1] = (SR * GL1 - SL * GR1 + SR * SL * (qR - qL)) * inv;
+    F[2] = F[0] * (Ss >= T(0) ? vL : vR);
 }
 
 }  // namespace swe

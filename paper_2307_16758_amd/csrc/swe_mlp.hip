@@ -278,7 +278,14 @@ __global__ void k_pairs(PairArgs<T> a)
         r[25] = float(T(0.5) * (ua + ub));
         r[26] = float(T(0.5) * (va + vb));
         r[27] = (ok && wet) ? 1.0f : 0.0f;
-        for (int i = 28; i < kRec; ++i) r[i] = 0.0f;
+        // the classic (minmod) interface values of the same half-edge, for
+        // comparing the two limiters against the same targets
+        const Half<T> mm = reconstruct<T, T4, kMUSCL, kMinmod>(Uc, Un[m], Un[ma], hn[ma], Un[mb], hn[mb],
+                                                               nx, ny, ge.w, di, 0.0f, eps);
+        r[28] = float(mm.h);
+        r[29] = float(mm.h + mm.b);
+        r[30] = float(mm.un);
+        r[31] = float(mm.ut);
     }
 }
 

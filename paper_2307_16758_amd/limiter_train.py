@@ -1,0 +1,166 @@
+"""Learned slope limiter: training-pair generation, training and equal-error
+evaluation, driven through the library's C ABI (every numerical step runs in
+libswe.so's kernels: the solver, the restriction, the feature and target
+extraction, the forward/backward passes and Adam; torch only holds device
+buffers and index vectors).
+
+Pairs: a scenario is run on its red-refined mesh (2x resolution, four
+children per coarse cell); at snapshot times the fine state is restricted to
+the coarse mesh and every coarse half-edge gives one record: the stencil
+features, the cell values and central slopes the limiter scales, and the
+fine solution's interface value as target.
+
+Evaluation: the coarse solver with the learned limiter and with the plain
+minmod / van Albada limiters, from the same initial state, against the
+restricted fine solution at the end time: L1(h) = sum |Omega| |h - R(h_fine)| /
+sum |Omega| over the coarse cells, and GPU seconds per simulated second.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import swe
+from .problem import prepare_scenario
+
+WV = np.array([1.0, 1.0, 0.25, 0.25], np.float32)   # weights of h, eta, u_n, u_t
+
+
+def init_params(seed=0):
+    """He-style initialisation; the output bias starts at 0 (phi = 0.5)."""
+    rng = np.random.default_rng(seed)
+    p = []
+    p.append(rng.normal(0, np.sqrt(2.0 / 14), 32 * 14))
+    p.append(np.zeros(32))
+    p.append(rng.normal(0, np.sqrt(2.0 / 32), 32 * 32))
+    p.append(np.zeros(32))
+    p.append(rng.normal(0, np.sqrt(1.0 / 32), 32))
+    p.append(np.zeros(1))
+    return np.concatenate(p).astype(np.float32)
+
+
+@dataclass
+class Pair:
+    coarse: object
+    fine: object
+    coarse_prep: object
+    fine_prep: object
+    children: object        # torch int32 [4 n_coarse]
+
+
+def _solver(prep, sc, limiter=swe.MINMOD, weights=None):
+    s = swe.Solver(precision=swe.F32, scheme=swe.MUSCL, integrator=swe.RK2, limiter=limiter)
+    s.mesh_upload(prep.mesh)
+    if sc.hydrograph is not None:
+        s.set_bc_series(*sc.hydrograph)
+    if weights is not None:
+        s.limiter_set_weights(weights)
+    l2g = prep.sub.l2g
+    s.set_state(sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    return s
+
+
+def make_pair(sc, fine_sc):
+    import torch
+    pc = prepare_scenario(sc)
+    pf = prepare_scenario(fine_sc)
+    g2l = np.empty(fine_sc.n_cells, np.int64)
+    g2l[pf.sub.l2g] = np.arange(pf.sub.n_total)
+    gid = pc.sub.l2g.astype(np.int64)
+    ch = np.stack([g2l[4 * gid + k] for k in range(4)], 1).astype(np.int32)
+    children = torch.from_numpy(ch.ravel().copy()).cuda()
+    return Pair(_solver(pc, sc), _solver(pf, fine_sc), pc, pf, children)
+
+
+def records(pair: Pair, t_snap):
+    """Run the fine solver to each snapshot time and collect the valid records
+    of the restricted coarse state (torch float32 [m, 32] on the device)."""
+    import torch
+    n = pair.coarse_prep.sub.n_total
+    buf = torch.empty(3 * n * swe.PAIR_RECORD, dtype=torch.float32, device="cuda")
+    out = []
+    for t in t_snap:
+        while pair.fine.time() < t:
+            pair.fine.step(6)
+        pair.coarse.limiter_pairs(pair.fine, pair.children, buf)
+        R = buf.view(-1, swe.PAIR_RECORD)
+        out.append(R[R[:, 27] == 1.0].clone())
+    return torch.cat(out, 0)
+
+
+def train(recs, params, epochs=20, batch=65536, lr=2e-3, seed=0, log=None):
+    import torch
+    tr = swe.Trainer(params)
+    n = recs.shape[0]
+    flat = recs.contiguous().view(-1)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(torch.int32).cuda()
+        tot, cnt = 0.0, 0
+        for i in range(0, n, batch):
+            idx = perm[i:i + batch]
+            tot += tr.step(flat, idx, WV, lr) * idx.numel()
+            cnt += idx.numel()
+        hist.append(tot / cnt)
+        if log:
+            log(f"epoch {ep} loss {tot / cnt:.6e}")
+    return tr.params(), hist
+
+
+def l1_depth(sol_h, ref_h, area):
+    return float((area * np.abs(sol_h - ref_h)).sum() / area.sum())
+
+
+def evaluate(sc, fine_sc, weights, t_end, limiters=(swe.MINMOD, swe.VANALBADA)):
+    """L1(h) of the coarse runs against the restricted fine run at t_end, and
+    GPU seconds per simulated second of each coarse run."""
+    import torch
+    pair = make_pair(sc, fine_sc)
+    while pair.fine.time() < t_end:
+        pair.fine.step(1)
+    t_fine = pair.fine.time()
+    fh = pair.fine.read_state()[0].astype(np.float64)
+    ch = pair.children.cpu().numpy().reshape(-1, 4)
+    ref = fh[ch].mean(1)
+    area = _areas(sc, pair.coarse_prep)
+    res = {}
+    for name, lim, w in [("learned", swe.LEARNED, weights)] + [(n_, l_, None) for n_, l_ in
+                                                               zip(("minmod", "vanalbada"), limiters)]:
+        s = _solver(pair.coarse_prep, sc, limiter=lim, weights=w)
+        torch.cuda.synchronize()
+        gpu = 0.0
+        steps = 0
+        while s.time() < t_fine - 1e-9:
+            dt = min(s.local_dt(), t_fine - s.time())
+            s.step(1, dt)
+            gpu += s.last_step_ms() * 1e-3
+            steps += 1
+        h = s.read_state()[0].astype(np.float64)
+        res[name] = dict(l1=l1_depth(h, ref, area), gpu_s_per_sim_s=gpu / t_fine, steps=steps)
+    return res
+
+
+def _areas(sc, prep):
+    p = sc.mesh.xy[sc.mesh.tri[prep.sub.l2g]]
+    return 0.5 * np.abs((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) -
+                        (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+
+
+def run_pipeline(train_scenarios, eval_scenarios, refine, t_snap, t_end, epochs=20, log=print):
+    """Generate pairs from ``train_scenarios`` (each refined by ``refine``),
+    train, evaluate on ``eval_scenarios``.  Returns (params, history, results)."""
+    import torch
+    t0 = time.time()
+    recs = []
+    for sc in train_scenarios:
+        pair = make_pair(sc, refine(sc))
+        recs.append(records(pair, t_snap))
+        del pair
+    R = torch.cat(recs, 0)
+    log(f"{R.shape[0]} records from {len(train_scenarios)} scenarios in {time.time() - t0:.1f} s")
+    params, hist = train(R, init_params(), epochs=epochs, log=log)
+    results = [evaluate(sc, refine(sc), params, t_end) for sc in eval_scenarios]
+    return params, hist, results

@@ -62,7 +62,7 @@ class swe_config(C.Structure):
                 ("integrator", C.c_int), ("limiter", C.c_int), ("waf_limiter", C.c_int),
                 ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
-                ("block", C.c_int), ("reserved", C.c_int * 7)]
+                ("block", C.c_int), ("cell_kernel", C.c_int), ("reserved", C.c_int * 6)]
 
 
 class swe_mesh(C.Structure):

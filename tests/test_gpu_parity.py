@@ -25,10 +25,12 @@ def _run_both(s, M, par, sc, l2g, nsteps, dt_fixed=0.0):
     return g, r
 
 
-def test_config1_hllc_fp64_cfl_mode():
-    """Config 1: 16,000-cell dam break, first-order HLLC, FP64, 200 CFL steps."""
+@pytest.mark.parametrize("cell_kernel", [0, 1])
+def test_config1_hllc_fp64_cfl_mode(cell_kernel):
+    """Config 1: 16,000-cell dam break, first-order HLLC, FP64, 200 CFL steps
+    (tiled kernel and one-thread-per-cell kernel)."""
     sc = config1()
-    s, M, par, pr = make_pair(sc, "hllc1", precision=1)
+    s, M, par, pr = make_pair(sc, "hllc1", precision=1, cell_kernel=cell_kernel)
     g, r = _run_both(s, M, par, sc, pr.sub.l2g, 200)
     errs = state_errors(g, r[:3], pr.sub.n_owned)
     assert max(errs) <= 1e-12, errs
@@ -49,10 +51,11 @@ def small_river(seed=2):
     return river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=seed)
 
 
+@pytest.mark.parametrize("cell_kernel", [0, 1])
 @pytest.mark.parametrize("name", ["muscl_minmod_rk2", "muscl_superbee_rk2", "muscl_vanalbada_rk2"])
-def test_river_muscl_fp64(name):
+def test_river_muscl_fp64(name, cell_kernel):
     sc = small_river()
-    s, M, par, pr = make_pair(sc, name, precision=1)
+    s, M, par, pr = make_pair(sc, name, precision=1, cell_kernel=cell_kernel)
     l2g = pr.sub.l2g
     dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
     g, r = _run_both(s, M, par, sc, l2g, 300, dt_fixed=dt)
@@ -60,12 +63,14 @@ def test_river_muscl_fp64(name):
     assert max(errs) <= 1e-10, errs
 
 
-def test_river_muscl_fp32_1000_steps():
+@pytest.mark.parametrize("cell_kernel,block", [(0, 256), (0, 64), (1, 256)])
+def test_river_muscl_fp32_1000_steps(cell_kernel, block):
     """Config-2 recipe at 10,240 cells (inflow, fixed-stage outflow, Manning,
     dry banks, bumps): FP32 MUSCL-HLLC-RK2 within 1e-4 of the FP64 oracle
-    after 1000 steps."""
+    after 1000 steps, for the kernel variants the autotuner chooses from."""
     sc = small_river()
-    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=0)
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=0, cell_kernel=cell_kernel,
+                              block=block)
     l2g = pr.sub.l2g
     dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
     g, r = _run_both(s, M, par, sc, l2g, 1000, dt_fixed=dt)
