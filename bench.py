@@ -61,6 +61,39 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def kernel_source_hash():
+    """sha256 of the device sources: a traffic figure measured on other
+    sources does not describe the present kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2307_16758_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per stage launch from the committed PMC summary of this
+    workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
+    None when it is absent or was taken on different kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"k_stage_{workload_name}_traffic.md")
+    if not os.path.exists(f):
+        return None
+    vals = {}
+    for line in open(f):
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(sc, kw, seconds):
     """Serial FP64 oracle on the same mesh: as many steps as fit in about
     ``seconds`` (at least one), one core."""
@@ -197,7 +230,8 @@ def main():
                    "cells": n_owned, "tuned_launch": tuned,
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload),
                      "kernel": "k_stage", "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_launch": per_launch_bytes},
         "health_bits": health,

@@ -22,6 +22,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-fno-hip-fp32-correctly-rounded-divide-sqrt",
              # FP32 denormals flushed (depths below eps are dry anyway)
              "-fgpu-flush-denormals-to-zero",
+             # multiply-adds fused only within one source expression, so
+             # that the same expression rounds the same wherever it is
+             # inlined (results independent of the tiling of the mesh)
+             "-ffp-contract=on",
              "-Wno-unused-result"] + os.environ.get("SWE_EXTRA_HIPFLAGS", "").split()
 
 

@@ -20,11 +20,13 @@ struct swe_ctx {
     size_t tsize = 4;
     // device buffers
     void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
+    void *he_co = nullptr, *he_lam = nullptr, *he_gam = nullptr;  // tiled kernel's half-edge set
     void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
     float *phi = nullptr;       // learned-limiter output, one per half-edge
     void *mlp = nullptr;        // learned-limiter weights (MlpDev, BF16)
     bool has_mlp = false;
-    swe::Clock *clock = nullptr;
+    unsigned long long *clock = nullptr;  // 3 slots x (1 + ncopy) lines per scenario
+    int ncopy = 64;
     swe::ScenParams *scen = nullptr;
     double *ser_t = nullptr, *ser_q = nullptr, *t0 = nullptr;
     int *health = nullptr, *flag = nullptr, *send_idx = nullptr;

@@ -12,6 +12,7 @@
 // results are deterministic run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -46,16 +47,141 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb)
     return x * base + (x < rem ? x : rem) + i;
 }
 
-__device__ __forceinline__ double step_dt(const Clock &c, double cfl, double dt_max, int rule,
-                                          double dt_fixed)
+using ClockWord = unsigned long long;
+
+// First word of clock slot `slot` of scenario s (the time); copy j of the
+// CFL partials starts kClockLine * (1 + j) words further.
+__host__ __device__ inline size_t clock_off(int ncopy, int s, int slot)
 {
-    if (dt_fixed > 0.0) return dt_fixed;
-    if (c.ratio_min == kInfBits) return dt_max > 0.0 ? dt_max : 0.0;  // nothing wet
-    double dt = rule == 1 ? cfl * bitsd(c.rad_min) / bitsd(c.lam_max) : cfl * bitsd(c.ratio_min);
+    return (size_t)(3 * s + slot) * (size_t)(ncopy + 1) * kClockLine;
+}
+
+// The CFL step (Sec. 6.2) from the reduced quantities; dt_max when nothing
+// is wet (no cell committed).
+__device__ __forceinline__ double cfl_dt(double mn, double mx, double cfl, double dt_max, int rule)
+{
+    if (!(mn < __builtin_huge_val())) return dt_max > 0.0 ? dt_max : 0.0;
+    double dt = rule == 1 ? cfl * mn / mx : cfl * mn;
     if (dt_max > 0.0 && dt > dt_max) dt = dt_max;
     return dt;
 }
 
+// Step of scenario s whose CFL partials are in clock slot `slot` (dt_fixed
+// when positive).  Every lane of the wave calls it; lanes with s < 0 get 0.
+// For each distinct scenario of the wave the copies are loaded one per lane
+// and reduced with shuffles, so all lanes agree bitwise.
+__device__ __forceinline__ double wave_step_dt(const ClockWord *clk, int ncopy, int slot, int s,
+                                               int rule, double cfl, double dt_max, double dt_fixed)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    const int lane = threadIdx.x & 63;
+    double dt = 0.0;
+    bool have = s < 0;
+    for (;;) {
+        const unsigned long long pend = __ballot(!have);
+        if (pend == 0ull) break;
+        const int S = __shfl(s, __builtin_ctzll(pend));
+        double mn = __builtin_huge_val(), mx = 0.0;
+        if (lane < ncopy) {
+            const ClockWord *q = clk + clock_off(ncopy, S, slot) + (size_t)(1 + lane) * kClockLine;
+            mn = bitsd(q[kCfqMin]);
+            mx = bitsd(q[kCfqMax]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o));
+            mx = fmax(mx, __shfl_xor(mx, o));
+        }
+        if (s == S) {
+            dt = cfl_dt(mn, mx, cfl, dt_max, rule);
+            have = true;
+        }
+    }
+    return dt;
+}
+
+// Per-cell CFL quantities (Sec. 6.2) of a wet owned cell: mn = R_i / lambda_i
+// (rule 0) or R_i (rule 1), mx = lambda_i; neutral values otherwise.
+struct CflVal {
+    double mn, mx;
+    int scen;  // -1: no cell
+};
+
+__device__ __forceinline__ CflVal cfl_none()
+{
+    CflVal v;
+    v.mn = __longlong_as_double((long long)kInfBits);
+    v.mx = 0.0;
+    v.scen = -1;
+    return v;
+}
+
+__device__ __forceinline__ CflVal cfl_cell(int rule, int scen, double R, double lam)
+{
+    CflVal v;
+    v.mn = rule == 1 ? R : R / lam;
+    v.mx = lam;
+    v.scen = scen;
+    return v;
+}
+
+// One commit of a block's (or lane's) partial: min mn always, max mx only
+// where the step rule reads it.
+__device__ __forceinline__ void cfl_atomic(ClockWord *q, int rule, const CflVal &v)
+{
+    atomicMin(&q[kCfqMin], dbits(v.mn));
+    if (rule == 1) atomicMax(&q[kCfqMax], dbits(v.mx));
+}
+
+// Block-wide reduction of the CFL quantities into clock slot `slot` of each
+// scenario: shuffles within each wave, the wave results through LDS, then
+// one thread commits one set of atomics per run of waves of the same
+// scenario (one set per block unless the block straddles two scenarios of a
+// batch; a wave that itself straddles commits per lane), to the block's
+// copy of the partials.  Same-address device atomics serialise, so their
+// number per address, not the cell work, would otherwise bound the stage.
+// Every thread of the block calls this; `part` holds one entry per wave and
+// may be reused after the next __syncthreads().
+__device__ __forceinline__ void cfl_commit(ClockWord *clk, int ncopy, int slot, int rule, CflVal v,
+                                           CflVal *part)
+{
+    const size_t copy = (size_t)(1 + (blockIdx.x & (ncopy - 1))) * kClockLine;
+    int smin = v.scen >= 0 ? v.scen : 0x7fffffff, smax = v.scen;
+    for (int o = 32; o > 0; o >>= 1) {
+        smin = min(smin, __shfl_xor(smin, o));
+        smax = max(smax, __shfl_xor(smax, o));
+    }
+    if (smin == smax) {
+        for (int o = 32; o > 0; o >>= 1) {
+            v.mn = fmin(v.mn, __shfl_xor(v.mn, o));
+            v.mx = fmax(v.mx, __shfl_xor(v.mx, o));
+        }
+        v.scen = smax;
+    } else {
+        if (v.scen >= 0 && v.mx > 0.0) cfl_atomic(clk + clock_off(ncopy, v.scen, slot) + copy, rule, v);
+        v.scen = -1;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = ((int)blockDim.x + 63) >> 6;
+        CflVal run = cfl_none();
+        for (int w = 0; w < nw; ++w) {
+            const CflVal p = part[w];
+            if (p.scen < 0 || !(p.mx > 0.0)) continue;
+            if (p.scen != run.scen) {
+                if (run.scen >= 0) cfl_atomic(clk + clock_off(ncopy, run.scen, slot) + copy, rule, run);
+                run = p;
+            } else {
+                run.mn = fmin(run.mn, p.mn);
+                run.mx = fmax(run.mx, p.mx);
+            }
+        }
+        if (run.scen >= 0) cfl_atomic(clk + clock_off(ncopy, run.scen, slot) + copy, rule, run);
+    }
+}
+
+// Total inflow discharge at time t: the scenario's hydrograph, linear
+// between its points and held constant outside them, else its constant.
 __device__ __forceinline__ double inflow_at(const ScenParams &s, const double *ts, const double *qs,
                                             double t)
 {
@@ -74,9 +200,12 @@ template <typename T> struct StageArgs {
     int n, n_scen;
     const int4 *nbr;
     const T4 *cell, *he_geo, *he_dist;
+    const T4 *he_co;             // per half-edge: nx, ny, d_mid / d_up, d_mid / d_fwd
+    const T *he_lam, *he_gam;    // per half-edge: L / area, d_mid / d_central
     const T4 *Uin, *U0;
     T4 *Uout;
-    Clock *clock;
+    ClockWord *clock;
+    int ncopy;                   // CFL partial copies per clock slot (power of two <= 64)
     const ScenParams *scen;
     const double *ser_t, *ser_q;
     const float *phi;
@@ -141,20 +270,49 @@ __device__ __forceinline__ bool waf_upwind(const T4 &Ua, bool ha, const T4 &Ub, 
     return ha || hb;
 }
 
-// One cell of one stage (all of Sec. 6.1 - 6.2 for cell c) followed by the
-// wave's share of the CFL reduction.  Every lane of the wave calls it.
+// Clock upkeep of a stage kernel: the first kernel of a step clears the
+// partials of slot step + 2 (spread over the grid); the last one advances
+// each scenario's time by its step (wave 0 of block s mod grid).
+template <typename T>
+__device__ __forceinline__ void clock_upkeep(const StageArgs<T> &a)
+{
+    if (a.kind != 2) {
+        const int ne = a.n_scen * a.ncopy;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+            ClockWord *q = a.clock + clock_off(a.ncopy, e / a.ncopy, a.slot_reset) +
+                           (size_t)(1 + e % a.ncopy) * kClockLine;
+            q[kCfqMin] = kInfBits;
+            q[kCfqMax] = 0ull;
+        }
+    }
+    if (a.kind != 1 && threadIdx.x < 64) {
+        for (int s = blockIdx.x; s < a.n_scen; s += gridDim.x) {
+            const double dt = wave_step_dt(a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl,
+                                           a.dt_max, a.dt_fixed);
+            if (threadIdx.x == 0)
+                a.clock[clock_off(a.ncopy, s, a.slot_next)] =
+                    dbits(bitsd(a.clock[clock_off(a.ncopy, s, a.slot_cur)]) + dt);
+        }
+    }
+}
+
+// One cell of one stage (all of Sec. 6.1 - 6.2 for cell c); returns the
+// cell's CFL quantities for the next step.
 template <typename T, int SCHEME, int LIM, int WAFM>
-__device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
+__device__ __forceinline__ CflVal stage_cell(const StageArgs<T> &a, const int c)
 {
     using T4 = typename V4<T>::type;
-    double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
-    int scen = -1;
+    CflVal cfl = cfl_none();
+    int4 nb4 = make_int4(-1, -1, -1, 0);
+    int s = -1;
     if (c < a.n) {
-        const int4 nb4 = a.nbr[c];
+        nb4 = a.nbr[c];
+        s = (int)((unsigned)nb4.w >> kScenShift);
+    }
+    const double dtd =
+        wave_step_dt(a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl, a.dt_max, a.dt_fixed);
+    if (c < a.n) {
         const unsigned word = (unsigned)nb4.w;
-        const int s = (int)(word >> kScenShift);
-        const Clock ck = a.clock[3 * s + a.slot_cur];
-        const double dtd = step_dt(ck, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
         const T dt = T(dtd);
         const T g = a.g, eps = a.eps;
         const T4 Uc = a.Uin[c];
@@ -175,7 +333,8 @@ __device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
             const int k = nbr[m];
             if (k < 0) {
                 const ScenParams sp = a.scen[s];
-                const double t_st = ck.t + (a.kind == 2 ? dtd : 0.0);
+                const double t_st =
+                    bitsd(a.clock[clock_off(a.ncopy, s, a.slot_cur)]) + (a.kind == 2 ? dtd : 0.0);
                 const T q_in = k == kBcInflow
                                    ? T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len)
                                    : T(0);
@@ -285,106 +444,72 @@ __device__ __forceinline__ void stage_cell(const StageArgs<T> &a, const int c)
         out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
         a.Uout[c] = out;
         if (flags) atomicOr(a.health, flags);
-        scen = s;
+        cfl.scen = s;
         if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
             const T u = fdiv(nu, nh), v = fdiv(nv, nh);
             const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-            ratio = double(fdiv(cg.y, lm));
-            rad = double(cg.y);
-            lam = double(lm);
+            cfl = cfl_cell(a.cfl_rule, s, double(cg.y), double(lm));
         }
     }
-    if (a.kind == 1) return;
-    // CFL reduction for the next step: wave-wide when the wave is one scenario
-    int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
-    for (int o = 32; o > 0; o >>= 1) {
-        smin = min(smin, __shfl_xor(smin, o));
-        smax = max(smax, __shfl_xor(smax, o));
-    }
-    if (smax < 0) return;  // the whole wave is past the end or dry
-    if (smin == smax) {
-        for (int o = 32; o > 0; o >>= 1) {
-            ratio = fmin(ratio, __shfl_xor(ratio, o));
-            rad = fmin(rad, __shfl_xor(rad, o));
-            lam = fmax(lam, __shfl_xor(lam, o));
-        }
-        if ((threadIdx.x & 63) == 0 && lam > 0.0) {
-            Clock &nx = a.clock[3 * smin + a.slot_next];
-            atomicMin(&nx.ratio_min, dbits(ratio));
-            atomicMin(&nx.rad_min, dbits(rad));
-            atomicMax(&nx.lam_max, dbits(lam));
-        }
-    } else if (scen >= 0 && lam > 0.0) {
-        Clock &nx = a.clock[3 * scen + a.slot_next];
-        atomicMin(&nx.ratio_min, dbits(ratio));
-        atomicMin(&nx.rad_min, dbits(rad));
-        atomicMax(&nx.lam_max, dbits(lam));
-    }
+    return cfl;
 }
 
 template <typename T, int SCHEME, int LIM, int WAFM>
 __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 {
-    if (blockIdx.x == 0) {
-        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
-            if (a.kind != 2) {  // first kernel of the step: clear the slot of step + 2
-                Clock &r = a.clock[3 * s + a.slot_reset];
-                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
-            }
-            if (a.kind != 1) {  // last kernel of the step: advance the time
-                const Clock cur = a.clock[3 * s + a.slot_cur];
-                a.clock[3 * s + a.slot_next].t =
-                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
-            }
-        }
-    }
+    clock_upkeep(a);
     // one tile per block, or (persistent launch, gridDim < tiles) a
     // grid-stride sweep; either way each XCD takes contiguous tiles
+    __shared__ CflVal part[4];
     const int ntiles = (a.n + (int)blockDim.x - 1) / (int)blockDim.x;
-    for (int t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
-        stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
+    for (int t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
+        const CflVal v = stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
+        if (a.kind != 1) {
+            cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, v, part);
+            __syncthreads();  // part is reused by the next tile
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
 // Tiled stage kernel (first-order HLLC and MUSCL-HLLC).  A block owns one
 // tile of TILE consecutive (Morton-ordered) cells:
 //  1. every thread forms the primitive values of its cell and its 1-ring,
-//     reconstructs its three half-edges into LDS, and files its edges as
-//     tasks: an edge to a cell of the same tile is filed once, by the cell
-//     that is the L side of the canonical orientation; an edge to a cell
-//     outside the tile is filed by each side;
+//     reconstructs its interior half-edges into LDS (with the centred bed
+//     term of each), and files its edges as tasks: an edge to a cell of the
+//     same tile is filed once, by the cell that is the L side of the
+//     canonical orientation; an edge to a cell outside the tile is filed by
+//     each side;
 //  2. the block runs the task lists densely (outside edges first: they also
 //     reconstruct the far side from its 2-ring; then inside edges, whose far
 //     side is already in LDS): hydrostatic reconstruction, HLLC in the
-//     canonical orientation, side corrections, results to LDS per half-edge;
-//  3. every thread sums its three half-edges (plus boundary fluxes and the
-//     centred bed term), updates, applies Manning and the cleanup.
+//     canonical orientation, side corrections; each half-edge's share
+//     replaces its interface values in LDS (a slot is read and written by
+//     one task only);
+//  3. every thread sums its three half-edges weighted by L / area (plus the
+//     boundary fluxes), updates, applies Manning and the cleanup, and the
+//     block commits its CFL quantities.
 // The flux of an edge is the same function of the same operands wherever it
-// is evaluated, so results do not depend on the tiling (sub-domain runs stay
-// bitwise equal to undecomposed runs) and contributions cancel bitwise.
+// is evaluated (operands selected, one evaluation, multiply-adds fused per
+// expression only), so results do not depend on the tiling (sub-domain runs
+// stay bitwise equal to undecomposed runs) and contributions cancel bitwise.
+// LDS per cell: 3 x (4 + 1) values + 3 16-bit task slots (18 KB per 256-cell
+// FP32 tile), so eight tiles fit a CU.
+#ifndef SWE_TILED_WAVES
+#define SWE_TILED_WAVES 6  // FP32: waves per SIMD the register budget is sized for
+#endif
 template <typename T, bool MUSCL_, int LIM, int TILE>
-__global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
+__global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? SWE_TILED_WAVES : 2)))
+k_stage_tiled(StageArgs<T> a)
 {
     using T4 = typename V4<T>::type;
-    __shared__ T4 sP[TILE];
+    static_assert(4 * TILE <= 65536, "16-bit task entries");
     __shared__ T4 sR[3 * TILE];
-    __shared__ T sF0[3 * TILE], sF1[3 * TILE], sF2[3 * TILE];
-    __shared__ int4 sNb[TILE];
-    __shared__ int sTask[2][3 * TILE];
+    __shared__ T sB[3 * TILE];
+    __shared__ unsigned short sTask[2][3 * TILE];
     __shared__ int sCount[2];
-    if (blockIdx.x == 0) {
-        for (int s = threadIdx.x; s < a.n_scen; s += blockDim.x) {
-            if (a.kind != 2) {
-                Clock &r = a.clock[3 * s + a.slot_reset];
-                r.ratio_min = kInfBits; r.rad_min = kInfBits; r.lam_max = 0ull;
-            }
-            if (a.kind != 1) {
-                const Clock cur = a.clock[3 * s + a.slot_cur];
-                a.clock[3 * s + a.slot_next].t =
-                    cur.t + step_dt(cur, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
-            }
-        }
-    }
+    __shared__ CflVal sCfl[TILE / 64];
+    clock_upkeep(a);
     const T g = a.g, eps = a.eps;
     const int ntiles = (a.n + TILE - 1) / TILE;
     for (int tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
@@ -395,7 +520,6 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
         // ---- 1: primitives, own half-edges, task lists
         int4 nb4 = make_int4(-1, -1, -1, 0);
         T4 Uc;
-        T4 ge[3];
         if (active) {
             nb4 = a.nbr[c];
             Uc = a.Uin[c];
@@ -409,35 +533,27 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
                 hn[m] = nb[m] >= 0;
                 pn[m] = hn[m] ? prim(a.Uin[nb[m]], eps) : pc;
             }
-            T4 pv;
-            pv.x = pc.h; pv.y = pc.b; pv.z = pc.u; pv.w = pc.v;
-            sP[cl] = pv;
-            sNb[cl] = nb4;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                ge[m] = a.he_geo[3 * c + m];
-                T4 dist;
-                dist.x = T(0); dist.y = T(0); dist.z = T(0); dist.w = T(0);
+                const int k = nb[m];
+                if (k < 0) continue;  // boundary half-edge: phase 3
+                const T4 co = a.he_co[3 * c + m];
+                T ga = T(0);
                 float phi = 0.0f;
-                if (MUSCL_ && hn[m]) {
-                    dist = a.he_dist[3 * c + m];
-                    if (LIM == kLearned) phi = a.phi[3 * c + m];
-                }
+                if (MUSCL_ && LIM == kLearned) { ga = a.he_gam[3 * c + m]; phi = a.phi[3 * c + m]; }
                 const int ma = (m + 1) % 3, mb = (m + 2) % 3;
-                const Half<T> r = recon2<T, T4, MUSCL_, LIM>(pc, pn[m], hn[m], pn[ma], hn[ma], pn[mb],
-                                                              hn[mb], ge[m].x, ge[m].y, ge[m].w,
-                                                              dist, phi, eps);
+                const Half<T> r = recon3<T, MUSCL_, LIM>(pc, pn[m], pn[ma], hn[ma], pn[mb], hn[mb],
+                                                          co.x, co.y, co.z, co.w, ga, phi, eps);
                 T4 rv;
                 rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
                 sR[3 * cl + m] = rv;
-                const int k = nb[m];
-                if (k >= 0) {
-                    const int kl = k - c0;
-                    if (kl >= 0 && kl < TILE) {
-                        if ((word >> (6 + m)) & 1u) sTask[1][atomicAdd(&sCount[1], 1)] = 4 * cl + m;
-                    } else {
-                        sTask[0][atomicAdd(&sCount[0], 1)] = 4 * cl + m;
-                    }
+                sB[3 * cl + m] = T(0.5) * g * (r.h + Uc.x) * (r.b - Uc.w);  // centred bed term
+                const int kl = k - c0;
+                if (kl >= 0 && kl < TILE) {
+                    if ((word >> (6 + m)) & 1u)
+                        sTask[1][atomicAdd(&sCount[1], 1)] = (unsigned short)(4 * cl + m);
+                } else {
+                    sTask[0][atomicAdd(&sCount[0], 1)] = (unsigned short)(4 * cl + m);
                 }
             }
         }
@@ -449,31 +565,29 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
             for (int i = threadIdx.x; i < nt; i += TILE) {
                 const int task = sTask[list][i];
                 const int tl = task >> 2, m = task & 3, tc = c0 + tl;
-                const int4 tn = sNb[tl];
+                const int4 tn = a.nbr[tc];
                 const unsigned word = (unsigned)tn.w;
                 const int k = m == 0 ? tn.x : (m == 1 ? tn.y : tn.z);
                 const int jb = (word >> (2 * m)) & 3;
                 const bool isL = (word >> (6 + m)) & 1u;
-                const T4 gm = a.he_geo[3 * tc + m];
-                const T nx = gm.x, ny = gm.y;
+                const T4 co = a.he_co[3 * tc + m];
+                const T nx = co.x, ny = co.y;
                 const T4 ov = sR[3 * tl + m];
+                const T sbo = sB[3 * tl + m];
                 T4 kv;
+                T sbk = T(0);
                 int kl = -1;
                 if (list == 1) {
                     kl = k - c0;
                     kv = sR[3 * kl + jb];
+                    sbk = sB[3 * kl + jb];
                 } else {
                     // far side: its own reconstruction across this edge, from its 2-ring
-                    const T4 Uk = a.Uin[k];
-                    const Prim<T> pk = prim(Uk, eps);
-                    const T4 pcv = sP[tl];
-                    Prim<T> pc;
-                    pc.h = pcv.x; pc.b = pcv.y; pc.u = pcv.z; pc.v = pcv.w;
+                    const Prim<T> pk = prim(a.Uin[k], eps);
+                    const Prim<T> pc = prim(a.Uin[tc], eps);
                     Prim<T> pka = pk, pkb = pk;
                     bool hka = false, hkb = false;
-                    T4 dk;
-                    dk.x = T(0); dk.y = T(0); dk.z = T(0); dk.w = T(0);
-                    T dmk = T(0);
+                    T al = T(0), be = T(0), ga = T(0);
                     float phik = 0.0f;
                     if (MUSCL_) {
                         const int4 nk = a.nbr[k];
@@ -483,79 +597,80 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
                         hkb = kb >= 0;
                         if (hka) pka = prim(a.Uin[ka], eps);
                         if (hkb) pkb = prim(a.Uin[kb], eps);
-                        dk = a.he_dist[3 * k + jb];
-                        dmk = a.he_geo[3 * k + jb].w;
-                        if (LIM == kLearned) phik = a.phi[3 * k + jb];
+                        const T4 ck = a.he_co[3 * k + jb];
+                        al = ck.z;
+                        be = ck.w;
+                        if (LIM == kLearned) { ga = a.he_gam[3 * k + jb]; phik = a.phi[3 * k + jb]; }
                     }
-                    const Half<T> r = recon2<T, T4, MUSCL_, LIM>(pk, pc, true, pka, hka, pkb, hkb, -nx,
-                                                                  -ny, dmk, dk, phik, eps);
+                    const Half<T> r = recon3<T, MUSCL_, LIM>(pk, pc, pka, hka, pkb, hkb, -nx, -ny, al,
+                                                              be, ga, phik, eps);
                     kv.x = r.h; kv.y = r.b; kv.z = r.un; kv.w = r.ut;
                 }
                 // hydrostatic reconstruction
-                const T be = tmax(ov.y, kv.y);
-                const T hso = tmax(T(0), ov.x + ov.y - be);
-                const T hsk = tmax(T(0), kv.x + kv.y - be);
+                const T bmax = tmax(ov.y, kv.y);
+                const T hso = tmax(T(0), ov.x + ov.y - bmax);
+                const T hsk = tmax(T(0), kv.x + kv.y - bmax);
+                // HLLC in the canonical orientation: operands selected, one
+                // evaluation, whichever side files the edge
+                const T hL = isL ? hso : hsk, uL = isL ? ov.z : kv.z, vL = isL ? ov.w : kv.w;
+                const T hR = isL ? hsk : hso, uR = isL ? -kv.z : -ov.z, vR = isL ? -kv.w : -ov.w;
+                const T nLx = isL ? nx : -nx, nLy = isL ? ny : -ny;
                 T F[3];
-                T nLx, nLy;
-                if (isL) {
-                    hllc_prim(g, eps, hso, ov.z, ov.w, hsk, -kv.z, -kv.w, F);
-                    nLx = nx; nLy = ny;
-                } else {
-                    hllc_prim(g, eps, hsk, kv.z, kv.w, hso, -ov.z, -ov.w, F);
-                    nLx = -nx; nLy = -ny;
-                }
+                hllc_prim(g, eps, hL, uL, vL, hR, uR, vR, F);
                 const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
                 const T sg = isL ? T(1) : T(-1);
-                const T po = T(0.5) * g * (ov.x * ov.x - hso * hso);
-                sF0[3 * tl + m] = sg * G0;
-                sF1[3 * tl + m] = sg * G1 + po * nx;
-                sF2[3 * tl + m] = sg * G2 + po * ny;
-                if (list == 1) {  // the other cell's half-edge (its normal is -n)
-                    const T pk_ = T(0.5) * g * (kv.x * kv.x - hsk * hsk);
-                    sF0[3 * kl + jb] = -(sg * G0);
-                    sF1[3 * kl + jb] = -(sg * G1) - pk_ * nx;
-                    sF2[3 * kl + jb] = -(sg * G2) - pk_ * ny;
+                T4 fo;
+                half_edge_flux(sg, G0, G1, G2, T(0.5) * g * (ov.x * ov.x - hso * hso) + sbo, nx, ny,
+                               fo.x, fo.y, fo.z);
+                fo.w = T(0);
+                sR[3 * tl + m] = fo;
+                if (list == 1) {  // the other cell's half-edge: normal -n, sign -sg
+                    T4 fk;
+                    half_edge_flux(-sg, G0, G1, G2, T(0.5) * g * (kv.x * kv.x - hsk * hsk) + sbk, -nx,
+                                   -ny, fk.x, fk.y, fk.z);
+                    fk.w = T(0);
+                    sR[3 * kl + jb] = fk;
                 }
             }
         }
         __syncthreads();
         // ---- 3: cell sums, update, friction, cleanup, CFL
-        double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
-        int scen = -1;
+        CflVal cfl = cfl_none();
+        const int s = active ? (int)((unsigned)nb4.w >> kScenShift) : -1;
+        const double dtd =
+            wave_step_dt(a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl, a.dt_max, a.dt_fixed);
         if (active) {
             const unsigned word = (unsigned)nb4.w;
-            const int s = (int)(word >> kScenShift);
-            const Clock ck = a.clock[3 * s + a.slot_cur];
-            const double dtd = step_dt(ck, a.cfl, a.dt_max, a.cfl_rule, a.dt_fixed);
             const T dt = T(dtd);
-            const T4 cg = a.cell[c];
             const int nb[3] = {nb4.x, nb4.y, nb4.z};
             T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const T nx = ge[m].x, ny = ge[m].y, L = ge[m].z;
+                const T lam = a.he_lam[3 * c + m];
                 if (nb[m] < 0) {
+                    const T4 co = a.he_co[3 * c + m];
                     const ScenParams sp = a.scen[s];
-                    const double t_st = ck.t + (a.kind == 2 ? dtd : 0.0);
+                    const double t_st = bitsd(a.clock[clock_off(a.ncopy, s, a.slot_cur)]) +
+                                        (a.kind == 2 ? dtd : 0.0);
                     const T q_in = nb[m] == kBcInflow
                                        ? T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len)
                                        : T(0);
                     T G[3];
-                    boundary_flux<T, T4>(nb[m], Uc, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
-                    acc0 += L * G[0];
-                    acc1 += L * G[1];
-                    acc2 += L * G[2];
+                    boundary_flux<T, T4>(nb[m], Uc, co.x, co.y, g, eps, q_in, T(sp.outflow_stage), G);
+                    acc0 += lam * G[0];
+                    acc1 += lam * G[1];
+                    acc2 += lam * G[2];
                 } else {
-                    const T4 rv = sR[3 * cl + m];
-                    const T sb = T(0.5) * g * (rv.x + Uc.x) * (rv.y - Uc.w);  // centred bed term
-                    acc0 += L * sF0[3 * cl + m];
-                    acc1 += L * (sF1[3 * cl + m] + sb * nx);
-                    acc2 += L * (sF2[3 * cl + m] + sb * ny);
+                    const T4 f = sR[3 * cl + m];
+                    acc0 += lam * f.x;
+                    acc1 += lam * f.y;
+                    acc2 += lam * f.z;
                 }
             }
-            T nh = Uc.x - dt * (acc0 * cg.x);
-            T nu = Uc.y - dt * (acc1 * cg.x);
-            T nv = Uc.z - dt * (acc2 * cg.x);
+            T nh = Uc.x - dt * acc0;
+            T nu = Uc.y - dt * acc1;
+            T nv = Uc.z - dt * acc2;
+            const T4 cg = a.cell[c];
             int flags = 0;
             if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
             if (nh < T(0)) {
@@ -581,101 +696,55 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled(StageArgs<T> a)
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
             a.Uout[c] = out;
             if (flags) atomicOr(a.health, flags);
-            scen = s;
+            cfl.scen = s;
             if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
                 const T r = frcp(nh);
                 const T u = nu * r, v = nv * r;
                 const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-                ratio = double(fdiv(cg.y, lm));
-                rad = double(cg.y);
-                lam = double(lm);
+                cfl = cfl_cell(a.cfl_rule, s, double(cg.y), double(lm));
             }
         }
-        if (a.kind != 1) {
-            int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
-            for (int o = 32; o > 0; o >>= 1) {
-                smin = min(smin, __shfl_xor(smin, o));
-                smax = max(smax, __shfl_xor(smax, o));
-            }
-            if (smax >= 0) {
-                if (smin == smax) {
-                    for (int o = 32; o > 0; o >>= 1) {
-                        ratio = fmin(ratio, __shfl_xor(ratio, o));
-                        rad = fmin(rad, __shfl_xor(rad, o));
-                        lam = fmax(lam, __shfl_xor(lam, o));
-                    }
-                    if ((threadIdx.x & 63) == 0 && lam > 0.0) {
-                        Clock &nx = a.clock[3 * smin + a.slot_next];
-                        atomicMin(&nx.ratio_min, dbits(ratio));
-                        atomicMin(&nx.rad_min, dbits(rad));
-                        atomicMax(&nx.lam_max, dbits(lam));
-                    }
-                } else if (scen >= 0 && lam > 0.0) {
-                    Clock &nx = a.clock[3 * scen + a.slot_next];
-                    atomicMin(&nx.ratio_min, dbits(ratio));
-                    atomicMin(&nx.rad_min, dbits(rad));
-                    atomicMax(&nx.lam_max, dbits(lam));
-                }
-            }
-        }
+        if (a.kind != 1) cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, cfl, sCfl);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
 
-// CFL minima of the current state into one clock slot (after set_state):
-// wave-wide reduction, one set of atomics per wave and scenario.
+// CFL minima of the current state into one clock slot (after set_state).
 template <typename T>
-__global__ void k_cfl_init(int n, const int4 *nbr, const typename V4<T>::type *cell,
-                           const typename V4<T>::type *U, Clock *clock, int slot, T g, T eps)
+__global__ void __launch_bounds__(256) k_cfl_init(int n, const int4 *nbr,
+                                                  const typename V4<T>::type *cell,
+                                                  const typename V4<T>::type *U, ClockWord *clock,
+                                                  int ncopy, int slot, int rule, T g, T eps)
 {
+    __shared__ CflVal part[4];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double ratio = __longlong_as_double((long long)kInfBits), rad = ratio, lam = 0.0;
-    int scen = -1;
+    CflVal v = cfl_none();
     if (c < n) {
         const unsigned word = (unsigned)nbr[c].w;
         const T h = U[c].x;
         if (((word >> kOwnedBit) & 1u) && h > eps) {
-            const T u = fdiv(U[c].y, h), v = fdiv(U[c].z, h);
-            const T lm = sqrt(u * u + v * v) + sqrt(g * h);
-            ratio = double(fdiv(cell[c].y, lm));
-            rad = double(cell[c].y);
-            lam = double(lm);
+            const T u = fdiv(U[c].y, h), w = fdiv(U[c].z, h);
+            const T lm = sqrt(u * u + w * w) + sqrt(g * h);
+            v = cfl_cell(rule, (int)(word >> kScenShift), double(cell[c].y), double(lm));
         }
-        scen = (int)(word >> kScenShift);
+        v.scen = (int)(word >> kScenShift);
     }
-    int smin = scen >= 0 ? scen : 0x7fffffff, smax = scen;
-    for (int o = 32; o > 0; o >>= 1) {
-        smin = min(smin, __shfl_xor(smin, o));
-        smax = max(smax, __shfl_xor(smax, o));
-    }
-    if (smax < 0) return;
-    if (smin == smax) {
-        for (int o = 32; o > 0; o >>= 1) {
-            ratio = fmin(ratio, __shfl_xor(ratio, o));
-            rad = fmin(rad, __shfl_xor(rad, o));
-            lam = fmax(lam, __shfl_xor(lam, o));
-        }
-        if ((threadIdx.x & 63) == 0 && lam > 0.0) {
-            Clock &k = clock[3 * smin + slot];
-            atomicMin(&k.ratio_min, dbits(ratio));
-            atomicMin(&k.rad_min, dbits(rad));
-            atomicMax(&k.lam_max, dbits(lam));
-        }
-    } else if (scen >= 0 && lam > 0.0) {
-        Clock &k = clock[3 * scen + slot];
-        atomicMin(&k.ratio_min, dbits(ratio));
-        atomicMin(&k.rad_min, dbits(rad));
-        atomicMax(&k.lam_max, dbits(lam));
-    }
+    cfl_commit(clock, ncopy, slot, rule, v, part);
 }
 
-__global__ void k_clock_reset(Clock *clock, int n_scen, int slot, const double *t0, int set_t)
+// Clock slot `slot` of every scenario: partials cleared, time set from t0
+// when set_t.  One thread per (scenario, copy).
+__global__ void k_clock_reset(ClockWord *clock, int ncopy, int n_scen, int slot, const double *t0,
+                              int set_t)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_scen) return;
-    Clock &k = clock[3 * s + slot];
-    k.ratio_min = kInfBits; k.rad_min = kInfBits; k.lam_max = 0ull;
-    if (set_t) k.t = t0[s];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_scen * ncopy) return;
+    const int s = e / ncopy, j = e % ncopy;
+    ClockWord *q = clock + clock_off(ncopy, s, slot);
+    if (set_t && j == 0) q[0] = dbits(t0[s]);
+    q += (size_t)(1 + j) * kClockLine;
+    q[kCfqMin] = kInfBits;
+    q[kCfqMax] = 0ull;
 }
 
 template <typename T>
@@ -765,10 +834,16 @@ void release_mesh(swe_ctx *c)
 {
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
     dfree(c->nbr); dfree(c->cell); dfree(c->he_geo); dfree(c->he_dist);
+    dfree(c->he_co); dfree(c->he_lam); dfree(c->he_gam);
     dfree(c->U[0]); dfree(c->U[1]); dfree(c->U1); dfree(c->tmp3); dfree(c->bed);
     dfree_t(c->phi); dfree_t(c->clock); dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
     dfree_t(c->t0); dfree_t(c->send_idx);
     c->has_mesh = c->has_state = false;
+}
+
+size_t clock_bytes(const swe_ctx *c)
+{
+    return sizeof(ClockWord) * clock_off(c->ncopy, c->n_scen, 0);
 }
 
 template <typename T>
@@ -794,6 +869,27 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
     to_t(g.he_dist, tmp);
     HIP_OK(c, hipMalloc(&c->he_dist, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_dist, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
+    // compact half-edge set of the tiled kernel, formed in double and
+    // rounded once: unit normal, the two MUSCL slope weights (the limiters
+    // are positively homogeneous of degree one, so d_mid * lim(sb, sf) =
+    // lim(d_mid sb, d_mid sf)), the learned limiter's central weight and the
+    // edge length over the cell area
+    std::vector<T> co(12 * n), lam(3 * n), gam(3 * n);
+    for (size_t h = 0; h < 3 * n; ++h) {
+        const double *ge = &g.he_geo[4 * h], *gd = &g.he_dist[4 * h];
+        co[4 * h + 0] = T(ge[0]);
+        co[4 * h + 1] = T(ge[1]);
+        co[4 * h + 2] = T(ge[3] * gd[0]);
+        co[4 * h + 3] = T(ge[3] * gd[1]);
+        lam[h] = T(ge[2] * g.cell[4 * (h / 3)]);
+        gam[h] = T(ge[3] * gd[2]);
+    }
+    HIP_OK(c, hipMalloc(&c->he_co, 12 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->he_co, co.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
+    HIP_OK(c, hipMalloc(&c->he_lam, 3 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->he_lam, lam.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
+    HIP_OK(c, hipMalloc(&c->he_gam, 3 * sizeof(T) * n));
+    HIP_OK(c, hipMemcpy(c->he_gam, gam.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
     return SWE_OK;
 }
 
@@ -881,7 +977,11 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.cell = (const T4 *)c->cell;
     a.he_geo = (const T4 *)c->he_geo;
     a.he_dist = (const T4 *)c->he_dist;
+    a.he_co = (const T4 *)c->he_co;
+    a.he_lam = (const T *)c->he_lam;
+    a.he_gam = (const T *)c->he_gam;
     a.clock = c->clock;
+    a.ncopy = c->ncopy;
     a.scen = c->scen;
     a.ser_t = c->ser_t;
     a.ser_q = c->ser_q;
@@ -1104,7 +1204,10 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     HIP_OK(c, hipMalloc(&c->tmp3, 3 * ts * n));
     HIP_OK(c, hipMalloc(&c->bed, ts * n));
     HIP_OK(c, hipMalloc(&c->phi, sizeof(float) * 3 * n));
-    HIP_OK(c, hipMalloc(&c->clock, sizeof(Clock) * 3 * (size_t)nm));
+    // CFL partial copies: enough lines that concurrent block commits rarely
+    // meet on one, few enough that large batches stay small
+    c->ncopy = nm <= 64 ? 64 : (nm <= 1024 ? 16 : 4);
+    HIP_OK(c, hipMalloc(&c->clock, clock_bytes(c)));
     HIP_OK(c, hipMalloc(&c->t0, sizeof(double) * (size_t)nm));
     {
         std::vector<double> bd(n);
@@ -1182,9 +1285,10 @@ int swe_scenario_times(swe_ctx *c, double *t)
     if (!c || !t) return set_err(c, SWE_ERR_ARG, "null");
     if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    std::vector<Clock> k(3 * (size_t)c->n_scen);
-    HIP_OK(c, hipMemcpy(k.data(), c->clock, sizeof(Clock) * k.size(), hipMemcpyDeviceToHost));
-    for (int s = 0; s < c->n_scen; ++s) t[s] = k[3 * s + c->step_count % 3].t;
+    std::vector<ClockWord> k(clock_bytes(c) / sizeof(ClockWord));
+    HIP_OK(c, hipMemcpy(k.data(), c->clock, clock_bytes(c), hipMemcpyDeviceToHost));
+    for (int s = 0; s < c->n_scen; ++s)
+        std::memcpy(&t[s], &k[clock_off(c->ncopy, s, (int)(c->step_count % 3))], sizeof(double));
     return health_status(c);
 }
 
@@ -1237,17 +1341,21 @@ int init_clock(swe_ctx *c, double t)
     HIP_OK(c, hipMemcpyAsync(c->t0, c->h_t0.data(), sizeof(double) * c->n_scen,
                              hipMemcpyHostToDevice, c->stream));
     // slot 0: time and CFL minima of the initial state; slot 1 cleared
-    const int gs = (c->n_scen + 63) / 64;
-    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(64), 0, c->stream, c->clock, c->n_scen, 0, c->t0, 1);
-    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(64), 0, c->stream, c->clock, c->n_scen, 1, c->t0, 0);
+    const int gs = (c->n_scen * c->ncopy + 255) / 256;
+    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(256), 0, c->stream, c->clock, c->ncopy, c->n_scen,
+                       0, c->t0, 1);
+    hipLaunchKernelGGL(k_clock_reset, dim3(gs), dim3(256), 0, c->stream, c->clock, c->ncopy, c->n_scen,
+                       1, c->t0, 0);
     if (ts == 8)
         hipLaunchKernelGGL(k_cfl_init<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
                            (const int4 *)c->nbr, (const double4 *)c->cell,
-                           (const double4 *)c->U[0], c->clock, 0, c->cfg.g, c->cfg.eps);
+                           (const double4 *)c->U[0], c->clock, c->ncopy, 0, c->cfg.cfl_rule,
+                           c->cfg.g, c->cfg.eps);
     else
         hipLaunchKernelGGL(k_cfl_init<float>, dim3(G), dim3(B), 0, c->stream, (int)n,
                            (const int4 *)c->nbr, (const float4 *)c->cell, (const float4 *)c->U[0],
-                           c->clock, 0, (float)c->cfg.g, (float)c->cfg.eps);
+                           c->clock, c->ncopy, 0, c->cfg.cfl_rule, (float)c->cfg.g,
+                           (float)c->cfg.eps);
     HIP_OK(c, hipGetLastError());
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->has_state = true;
@@ -1338,16 +1446,16 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     // save the state, clocks and step index; every candidate starts from them
     const size_t bytes = 4 * c->tsize * (size_t)c->n_total;
     void *saveU = nullptr;
-    Clock *saveK = nullptr;
+    void *saveK = nullptr;
     HIP_OK(c, hipMalloc(&saveU, bytes));
-    if (hipMalloc(&saveK, sizeof(Clock) * 3 * (size_t)c->n_scen) != hipSuccess) {
+    if (hipMalloc(&saveK, clock_bytes(c)) != hipSuccess) {
         (void)hipFree(saveU);
         return set_err(c, SWE_ERR_OOM, "autotune buffers");
     }
     const long long step0 = c->step_count;
     void *Ucur = c->U[step0 & 1];
     HIP_OK(c, hipMemcpyAsync(saveU, Ucur, bytes, hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(saveK, c->clock, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(saveK, c->clock, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     const bool graphs = c->use_graphs;
     c->use_graphs = false;
     float best = 1e30f;
@@ -1362,7 +1470,7 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
             c->block = B;
             c->grid_persist = persist ? ncu * (2048 / B) : 0;
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
-            (void)hipMemcpyAsync(c->clock, saveK, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream);
+            (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
             c->step_count = step0;
             rc = swe_step(c, 2, 0.0);  // warm-up
             if (rc != SWE_OK) break;
@@ -1380,7 +1488,7 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     c->grid_persist = best_g;
     c->cfg.cell_kernel = best_cell;
     (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
-    (void)hipMemcpyAsync(c->clock, saveK, sizeof(Clock) * 3 * c->n_scen, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);
     c->step_count = step0;
     (void)hipFree(saveU);
@@ -1413,9 +1521,8 @@ int swe_time(swe_ctx *c, double *t)
     if (!c || !t) return set_err(c, SWE_ERR_ARG, "null");
     if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    Clock k;
-    HIP_OK(c, hipMemcpy(&k, c->clock + (c->step_count % 3), sizeof(Clock), hipMemcpyDeviceToHost));
-    *t = k.t;
+    HIP_OK(c, hipMemcpy(t, c->clock + clock_off(c->ncopy, 0, (int)(c->step_count % 3)),
+                        sizeof(double), hipMemcpyDeviceToHost));
     return health_status(c);
 }
 
@@ -1424,17 +1531,25 @@ int swe_local_dt(swe_ctx *c, double *dt)
     if (!c || !dt) return set_err(c, SWE_ERR_ARG, "null");
     if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    Clock k;
-    HIP_OK(c, hipMemcpy(&k, c->clock + (c->step_count % 3), sizeof(Clock), hipMemcpyDeviceToHost));
+    // reduce the copies of scenario 0's current slot, as the kernels do
+    const int nc = c->ncopy;
+    std::vector<ClockWord> k((size_t)(nc + 1) * kClockLine);
+    HIP_OK(c, hipMemcpy(k.data(), c->clock + clock_off(nc, 0, (int)(c->step_count % 3)),
+                        sizeof(ClockWord) * k.size(), hipMemcpyDeviceToHost));
+    ClockWord mnb = kInfBits, mxb = 0ull;
+    for (int j = 0; j < nc; ++j) {
+        const ClockWord *q = &k[(size_t)(1 + j) * kClockLine];
+        mnb = std::min(mnb, q[kCfqMin]);
+        mxb = std::max(mxb, q[kCfqMax]);
+    }
     double v;
-    if (k.ratio_min == kInfBits) {
+    if (mnb == kInfBits) {  // nothing wet
         v = c->cfg.dt_max > 0 ? c->cfg.dt_max : 0.0;
     } else {
-        double r, rad, lam;
-        std::memcpy(&r, &k.ratio_min, 8);
-        std::memcpy(&rad, &k.rad_min, 8);
-        std::memcpy(&lam, &k.lam_max, 8);
-        v = c->cfg.cfl_rule == 1 ? c->cfg.cfl * rad / lam : c->cfg.cfl * r;
+        double mn, mx;
+        std::memcpy(&mn, &mnb, 8);
+        std::memcpy(&mx, &mxb, 8);
+        v = c->cfg.cfl_rule == 1 ? c->cfg.cfl * mn / mx : c->cfg.cfl * mn;
         if (c->cfg.dt_max > 0 && v > c->cfg.dt_max) v = c->cfg.dt_max;
     }
     *dt = v;

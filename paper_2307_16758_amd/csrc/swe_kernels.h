@@ -21,14 +21,15 @@ enum { kHealthNonfinite = 1, kHealthNegDepth = 2, kHealthClipped = 4 };
 
 // Per-scenario step clock, three slots per scenario rotating with the step
 // index: the current step reads slot s, reduces the next CFL step into slot
-// s+1 and clears slot s+2.  CFL minima are kept as the bit patterns of
-// non-negative doubles, whose integer order is their numeric order.
-struct Clock {
-    double t;
-    unsigned long long ratio_min;  // min over wet owned cells of R_i / lambda_i
-    unsigned long long rad_min;    // min R_i over wet owned cells
-    unsigned long long lam_max;    // max lambda_i over wet owned cells
-};
+// s+1 and clears slot s+2.  A slot is 1 + ncopy cache lines of 128 bytes:
+// the time (double) in the first, then ncopy partials of the CFL quantities
+// over wet owned cells: the minimum of R_i / lambda_i (rule 0) or of R_i
+// (rule 1), and the maximum of lambda_i, as the bit patterns of non-negative
+// doubles, whose integer order is their numeric order.  Blocks commit to
+// copy (block index mod ncopy), so concurrent atomics spread over ncopy
+// lines; readers reduce the copies.
+constexpr int kClockLine = 16;  // 64-bit words per 128-byte line
+enum { kCfqMin = 0, kCfqMax = 1 };
 
 struct ScenParams {
     double inflow_q;         // constant total discharge
@@ -266,6 +267,17 @@ __device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], con
 
 namespace swe {
 
+// tanh for the limiter features: exact in FP64; in FP32 through one hardware
+// exp2 and one reciprocal (about 1e-6 absolute, far below the BF16 rounding
+// the features then get).
+template <typename T> __device__ __forceinline__ T ftanh(T x) { return tanh(x); }
+template <> __device__ __forceinline__ float ftanh<float>(float x)
+{
+    const float xc = fminf(fmaxf(x, -15.0f), 15.0f);
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * xc);  // exp(2x)
+    return (e - 1.0f) * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 constexpr int kMlpIn = 14, kMlpH = 32;
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;  // 1569
 
@@ -302,19 +314,20 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
     const T hc = Uc.x;
     const T sh = hc + T(0.01), sq = hc * sqrt(g * hc) + T(0.01);
     const T sc[4] = {sh, sq, sq, sh};
-    const T du = T(1) / dist.x, df = dist.w;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const T sb = (qc[k] - qu[k]) / du, sf = (qk[k] - qc[k]) / df;
-        f[3 * k + 0] = float(tanh(sb * dm / sc[k]));
-        f[3 * k + 1] = float(tanh(sf * dm / sc[k]));
-        const T r = sb * sf / (sf * sf + T(1e-12));
+        const T sb = (qc[k] - qu[k]) * dist.x, sf = (qk[k] - qc[k]) * dist.y;
+        const T isc = frcp(sc[k]);
+        f[3 * k + 0] = float(ftanh(sb * dm * isc));
+        f[3 * k + 1] = float(ftanh(sf * dm * isc));
+        const T r = fdiv(sb * sf, sf * sf + T(1e-12));
         f[3 * k + 2] = float(tmin(T(2), tmax(T(-2), r)));
     }
-    const T uc = Uc.y / hc, vc = Uc.z / hc;
+    const T ih = frcp(hc);
+    const T uc = Uc.y * ih, vc = Uc.z * ih;
     const T un = uc * nx + vc * ny, ut = -uc * ny + vc * nx;
-    f[12] = float(tanh(sqrt(un * un + ut * ut) / sqrt(g * tmax(hc, T(1e-6)))));
-    f[13] = float(tanh((Uk.x - hc) / (hc + T(0.01))));
+    f[12] = float(ftanh(fdiv(sqrt(un * un + ut * ut), sqrt(g * tmax(hc, T(1e-6))))));
+    f[13] = float(ftanh(fdiv(Uk.x - hc, hc + T(0.01))));
     return true;
 }
 
@@ -416,6 +429,63 @@ __device__ __forceinline__ Half<T> recon2(const Prim<T> &C, const Prim<T> &K, bo
     return r;
 }
 
+// Interface values of cell C across an interior edge with outward normal n
+// (Sec. 6.2.3 on the rotated states), K across the edge, A and B the upwind
+// cells, with the distances folded into weights: al = d_mid / d_up and
+// be = d_mid / d_fwd for the limited slope, ga = d_mid / d_central for the
+// learned limiter's scaled central slope.
+template <typename T, bool MUSCL_, int LIM>
+__device__ __forceinline__ Half<T> recon3(const Prim<T> &C, const Prim<T> &K, const Prim<T> &A,
+                                          bool ha, const Prim<T> &B, bool hb, T nx, T ny, T al,
+                                          T be, T ga, float phi, T eps)
+{
+    Half<T> r;
+    r.h = C.h;
+    r.b = C.b;
+    r.un = C.u * nx + C.v * ny;
+    r.ut = -C.u * ny + C.v * nx;
+    if (!MUSCL_) return r;
+    if (!(C.h > eps) || !(K.h > eps)) return r;
+    if ((ha && !(A.h > eps)) || (hb && !(B.h > eps)) || (!ha && !hb)) return r;
+    const T qc[4] = {C.h, C.h + C.b, r.un, r.ut};
+    const T qk[4] = {K.h, K.h + K.b, K.u * nx + K.v * ny, -K.u * ny + K.v * nx};
+    T qu[4];
+    if (ha && hb) {
+        qu[0] = T(0.5) * (A.h + B.h);
+        qu[1] = T(0.5) * ((A.h + A.b) + (B.h + B.b));
+        qu[2] = T(0.5) * ((A.u * nx + A.v * ny) + (B.u * nx + B.v * ny));
+        qu[3] = T(0.5) * ((-A.u * ny + A.v * nx) + (-B.u * ny + B.v * nx));
+    } else {
+        const Prim<T> &O = ha ? A : B;
+        qu[0] = O.h;
+        qu[1] = O.h + O.b;
+        qu[2] = O.u * nx + O.v * ny;
+        qu[3] = -O.u * ny + O.v * nx;
+    }
+    T out[4];
+    bool done = false;
+    if (LIM == kLearned) {
+        if (phi >= 0.0f && phi <= 1.0f) {
+            const T p = T(phi);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[i] = qc[i] + p * (ga * (qk[i] - qu[i]));
+            done = out[0] >= T(0);
+        }
+    }
+    if (!done) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[i] = qc[i] + limit2<T, (LIM == kLearned ? kMinmod : LIM)>(al * (qc[i] - qu[i]),
+                                                                          be * (qk[i] - qc[i]));
+    }
+    if (out[0] < T(0)) return r;
+    r.h = out[0];
+    r.b = out[1] - out[0];
+    r.un = out[2];
+    r.ut = out[3];
+    return r;
+}
+
 // HLLC of Sec. 6.2.1 from depths and normal-frame velocities (the same
 // estimates as wave_fan / flux_hllc).
 template <typename T>
@@ -456,6 +526,19 @@ __device__ __forceinline__ void hllc_prim(T g, T eps, T hL, T uL, T vL, T hR, T 
     F[0] = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
     F[1] = (SR * GL1 - SL * GR1 + SR * SL * (qR - qL)) * inv;
     F[2] = F[0] * (Ss >= T(0) ? vL : vR);
+}
+
+// A cell's share of an edge (Sec. 6.1): the oriented flux sg * G plus the
+// side correction p along the cell's own normal, as explicit fused
+// multiply-adds so that both cells of an edge, and both places an edge can
+// be evaluated, round identically.
+template <typename T>
+__device__ __forceinline__ void half_edge_flux(T sg, T G0, T G1, T G2, T p, T nx, T ny, T &f0,
+                                               T &f1, T &f2)
+{
+    f0 = sg * G0;
+    f1 = fma(p, nx, sg * G1);
+    f2 = fma(p, ny, sg * G2);
 }
 
 }  // namespace swe

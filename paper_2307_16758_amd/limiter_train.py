@@ -164,3 +164,110 @@ def run_pipeline(train_scenarios, eval_scenarios, refine, t_snap, t_end, epochs=
     params, hist = train(R, init_params(), epochs=epochs, log=log)
     results = [evaluate(sc, refine(sc), params, t_end) for sc in eval_scenarios]
     return params, hist, results
+
+
+def _run_to(s, t_end):
+    """Step a solver in CFL mode to exactly t_end; returns GPU seconds."""
+    gpu = 0.0
+    while s.time() < t_end - 1e-9:
+        dt = min(s.local_dt(), t_end - s.time())
+        s.step(1, dt)
+        gpu += s.last_step_ms() * 1e-3
+    return gpu
+
+
+def _descendants(coarse_prep, fine_prep, levels, n_fine_global):
+    """Fine local index of the 4**levels red-refinement descendants of every
+    coarse local cell (fine gid = 4**levels * coarse gid + offset)."""
+    g2l = np.empty(n_fine_global, np.int64)
+    g2l[fine_prep.sub.l2g] = np.arange(fine_prep.sub.n_total)
+    f = 4 ** levels
+    gid = coarse_prep.sub.l2g.astype(np.int64)
+    return g2l[f * gid[:, None] + np.arange(f)[None, :]]
+
+
+def evaluate_ladder(sc, weights, t_end, log=print):
+    """Equal-error comparison on nested meshes.  Reference: the scenario on
+    the mesh refined twice (16 cells per coarse cell), restricted to the
+    coarse mesh.  Runs: learned, minmod and van Albada on the coarse mesh, and
+    minmod on the once-refined mesh (the next rung of the plain limiter's
+    cost-error ladder), all restricted to the coarse mesh.  The plain
+    limiter's cost at the learned limiter's error is interpolated log-log
+    between its two rungs."""
+    from swe_inputs import refine_scenario
+    s1 = refine_scenario(sc)
+    s2 = refine_scenario(s1)
+    pc, p1, p2 = prepare_scenario(sc), prepare_scenario(s1), prepare_scenario(s2)
+    ref = _solver(p2, s2)
+    _run_to(ref, t_end)
+    h2 = ref.read_state()[0].astype(np.float64)
+    ref_h = h2[_descendants(pc, p2, 2, s2.n_cells)].mean(1)
+    del ref
+    area = _areas(sc, pc)
+    out = {}
+    for name, prep, scen, lim, w, lev in [
+            ("learned", pc, sc, swe.LEARNED, weights, 0),
+            ("minmod", pc, sc, swe.MINMOD, None, 0),
+            ("vanalbada", pc, sc, swe.VANALBADA, None, 0),
+            ("minmod_2x", p1, s1, swe.MINMOD, None, 1)]:
+        s = _solver(prep, scen, limiter=lim, weights=w)
+        gpu = _run_to(s, t_end)
+        h = s.read_state()[0].astype(np.float64)
+        if lev:
+            h = h[_descendants(pc, p1, 1, s1.n_cells)].mean(1)
+        out[name] = dict(l1=l1_depth(h, ref_h, area), gpu_s_per_sim_s=gpu / t_end,
+                         cells=prep.sub.n_total)
+        log(f"  {name}: L1(h) {out[name]['l1']:.4e}  GPU s / sim s {gpu / t_end:.4e}")
+    e0, c0 = out["minmod"]["l1"], out["minmod"]["gpu_s_per_sim_s"]
+    e1, c1 = out["minmod_2x"]["l1"], out["minmod_2x"]["gpu_s_per_sim_s"]
+    el = out["learned"]["l1"]
+    if e1 < el <= e0 and e0 > e1:
+        w_ = (np.log(e0) - np.log(el)) / (np.log(e0) - np.log(e1))
+        out["minmod_cost_at_learned_error"] = float(np.exp(np.log(c0) + w_ * (np.log(c1) - np.log(c0))))
+    elif el <= e1:
+        out["minmod_cost_at_learned_error"] = ">= " + repr(c1)
+    else:
+        out["minmod_cost_at_learned_error"] = "<= " + repr(c0)
+    return out
+
+
+def main(argv=None):
+    """Equal-error study of the learned limiter (config-4 recipe, scaled by
+    the command-line sizes): train on seeded channel scenarios; for held-out
+    scenarios compare L1(h) and cost per simulated second (evaluate_ladder)."""
+    import argparse
+    import json
+
+    from swe_inputs import river_channel, refine_scenario
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=12)
+    ap.add_argument("--held-out", type=int, default=4)
+    ap.add_argument("--nx", type=int, default=400)
+    ap.add_argument("--ny", type=int, default=80)
+    ap.add_argument("--t-end", type=float, default=60.0)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    rng = np.random.default_rng(4)
+
+    def scen(seed):
+        return river_channel(Lx=10000.0, Ly=2000.0, nx=a.nx, ny=a.ny, seed=seed,
+                             inflow_q=float(rng.uniform(200.0, 2000.0)))
+
+    tr = [scen(1000 + i) for i in range(a.train)]
+    snaps = list(np.linspace(a.t_end / 4, a.t_end, 4))
+    params, hist, _ = run_pipeline(tr, [], refine_scenario, snaps, a.t_end, epochs=a.epochs)
+    out = dict(train=a.train, nx=a.nx, ny=a.ny, t_end=a.t_end, loss_history=hist, held_out=[])
+    for i in range(a.held_out):
+        sc = scen(1180 + i)
+        print(f"held-out scenario {1180 + i}", flush=True)
+        res = evaluate_ladder(sc, params, a.t_end)
+        out["held_out"].append(dict(seed=1180 + i, inflow_q=sc.inflow_q, **res))
+        print(json.dumps(out["held_out"][-1]), flush=True)
+    if a.out:
+        json.dump(dict(out, params=params.tolist()), open(a.out, "w"))
+    return out
+
+
+if __name__ == "__main__":
+    main()

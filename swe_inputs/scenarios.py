@@ -265,7 +265,7 @@ def ensemble_scenarios(n=64, seed_base=5000, min_cells=5.0e4, max_cells=2.0e6,
         nx = 5 * ny
         q_peak = rng.uniform(100.0, 2000.0)
         t_peak = rng.uniform(30.0, 90.0)
-        width = rng.uniform(30.0, 90.0)
+        width = rng.uniform(0.2, 0.9) * t_peak      # rise starts after t = 0
         manning = rng.uniform(0.02, 0.05)
         hyd = (np.array([0.0, t_peak - width, t_peak, t_peak + width, 1.0e9]),
                np.array([100.0, 100.0, q_peak, 100.0, 100.0]))
