@@ -103,7 +103,8 @@ typedef struct {
     double cfl;        /* default 0.45 */
     double eps;        /* wet/dry threshold [m], default 1e-6 */
     double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
-    int block;         /* threads per block = cells per tile: 64, 128 or 256 (0: 256) */
+    int block;         /* threads per block = cells per tile: 64, 128, 256 or 512 (0: 256);
+                          the one-thread-per-cell kernel uses at most 256 */
     int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the
                           tiled kernel for HLLC1 and MUSCL (WAF always uses the cell kernel) */
     int reserved[6];
@@ -172,7 +173,7 @@ int swe_batch_offsets(const swe_ctx *ctx, int32_t *n_scenarios, int32_t *offsets
 int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
 
 /* Autotuner: times n_steps CFL steps for each launch shape (tiled or cell
- * kernel; 64, 128 or 256 threads per block; one tile per block or a
+ * kernel; 64, 128, 256 or 512 (tiled only) threads per block; one tile per block or a
  * persistent grid of 2048 / block blocks per compute unit) from the current
  * state, keeps the fastest and restores the state, clocks and time.  The
  * choice never changes results (every variant computes the same values).

@@ -81,13 +81,12 @@ __device__ __forceinline__ double wave_step_dt(const ClockWord *clk, int ncopy, 
         const unsigned long long pend = __ballot(!have);
         if (pend == 0ull) break;
         const int S = __shfl(s, __builtin_ctzll(pend));
-        double mn = __builtin_huge_val(), mx = 0.0;
-        if (lane < ncopy) {
-            const ClockWord *q = clk + clock_off(ncopy, S, slot) + (size_t)(1 + lane) * kClockLine;
-            mn = bitsd(q[kCfqMin]);
-            mx = bitsd(q[kCfqMax]);
-        }
-        for (int o = 32; o > 0; o >>= 1) {
+        // every group of ncopy lanes loads all copies, so the butterfly
+        // within the group leaves the full reduction in every lane
+        const ClockWord *q =
+            clk + clock_off(ncopy, S, slot) + (size_t)(1 + (lane & (ncopy - 1))) * kClockLine;
+        double mn = bitsd(q[kCfqMin]), mx = bitsd(q[kCfqMax]);
+        for (int o = ncopy >> 1; o > 0; o >>= 1) {
             mn = fmin(mn, __shfl_xor(mn, o));
             mx = fmax(mx, __shfl_xor(mx, o));
         }
@@ -99,26 +98,28 @@ __device__ __forceinline__ double wave_step_dt(const ClockWord *clk, int ncopy, 
     return dt;
 }
 
-// Per-cell CFL quantities (Sec. 6.2) of a wet owned cell: mn = R_i / lambda_i
-// (rule 0) or R_i (rule 1), mx = lambda_i; neutral values otherwise.
-struct CflVal {
-    double mn, mx;
+// Per-cell CFL quantities (Sec. 6.2) of a wet owned cell, in the working
+// precision: mn = R_i / lambda_i (rule 0) or R_i (rule 1), mx = lambda_i;
+// neutral values otherwise.  They become doubles only when committed (the
+// conversion is monotonic, so reducing before or after it agrees).
+template <typename T> struct CflVal {
+    T mn, mx;
     int scen;  // -1: no cell
 };
 
-__device__ __forceinline__ CflVal cfl_none()
+template <typename T> __device__ __forceinline__ CflVal<T> cfl_none()
 {
-    CflVal v;
-    v.mn = __longlong_as_double((long long)kInfBits);
-    v.mx = 0.0;
+    CflVal<T> v;
+    v.mn = T(__builtin_huge_val());
+    v.mx = T(0);
     v.scen = -1;
     return v;
 }
 
-__device__ __forceinline__ CflVal cfl_cell(int rule, int scen, double R, double lam)
+template <typename T> __device__ __forceinline__ CflVal<T> cfl_cell(int rule, int scen, T R, T lam)
 {
-    CflVal v;
-    v.mn = rule == 1 ? R : R / lam;
+    CflVal<T> v;
+    v.mn = rule == 1 ? R : fdiv(R, lam);
     v.mx = lam;
     v.scen = scen;
     return v;
@@ -126,10 +127,11 @@ __device__ __forceinline__ CflVal cfl_cell(int rule, int scen, double R, double 
 
 // One commit of a block's (or lane's) partial: min mn always, max mx only
 // where the step rule reads it.
-__device__ __forceinline__ void cfl_atomic(ClockWord *q, int rule, const CflVal &v)
+template <typename T>
+__device__ __forceinline__ void cfl_atomic(ClockWord *q, int rule, const CflVal<T> &v)
 {
-    atomicMin(&q[kCfqMin], dbits(v.mn));
-    if (rule == 1) atomicMax(&q[kCfqMax], dbits(v.mx));
+    atomicMin(&q[kCfqMin], dbits(double(v.mn)));
+    if (rule == 1) atomicMax(&q[kCfqMax], dbits(double(v.mx)));
 }
 
 // Block-wide reduction of the CFL quantities into clock slot `slot` of each
@@ -141,8 +143,9 @@ __device__ __forceinline__ void cfl_atomic(ClockWord *q, int rule, const CflVal 
 // number per address, not the cell work, would otherwise bound the stage.
 // Every thread of the block calls this; `part` holds one entry per wave and
 // may be reused after the next __syncthreads().
-__device__ __forceinline__ void cfl_commit(ClockWord *clk, int ncopy, int slot, int rule, CflVal v,
-                                           CflVal *part)
+template <typename T>
+__device__ __forceinline__ void cfl_commit(ClockWord *clk, int ncopy, int slot, int rule,
+                                           CflVal<T> v, CflVal<T> *part)
 {
     const size_t copy = (size_t)(1 + (blockIdx.x & (ncopy - 1))) * kClockLine;
     int smin = v.scen >= 0 ? v.scen : 0x7fffffff, smax = v.scen;
@@ -157,17 +160,17 @@ __device__ __forceinline__ void cfl_commit(ClockWord *clk, int ncopy, int slot, 
         }
         v.scen = smax;
     } else {
-        if (v.scen >= 0 && v.mx > 0.0) cfl_atomic(clk + clock_off(ncopy, v.scen, slot) + copy, rule, v);
+        if (v.scen >= 0 && v.mx > T(0)) cfl_atomic(clk + clock_off(ncopy, v.scen, slot) + copy, rule, v);
         v.scen = -1;
     }
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = ((int)blockDim.x + 63) >> 6;
-        CflVal run = cfl_none();
+        CflVal<T> run = cfl_none<T>();
         for (int w = 0; w < nw; ++w) {
-            const CflVal p = part[w];
-            if (p.scen < 0 || !(p.mx > 0.0)) continue;
+            const CflVal<T> p = part[w];
+            if (p.scen < 0 || !(p.mx > T(0))) continue;
             if (p.scen != run.scen) {
                 if (run.scen >= 0) cfl_atomic(clk + clock_off(ncopy, run.scen, slot) + copy, rule, run);
                 run = p;
@@ -299,10 +302,10 @@ __device__ __forceinline__ void clock_upkeep(const StageArgs<T> &a)
 // One cell of one stage (all of Sec. 6.1 - 6.2 for cell c); returns the
 // cell's CFL quantities for the next step.
 template <typename T, int SCHEME, int LIM, int WAFM>
-__device__ __forceinline__ CflVal stage_cell(const StageArgs<T> &a, const int c)
+__device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int c)
 {
     using T4 = typename V4<T>::type;
-    CflVal cfl = cfl_none();
+    CflVal<T> cfl = cfl_none<T>();
     int4 nb4 = make_int4(-1, -1, -1, 0);
     int s = -1;
     if (c < a.n) {
@@ -448,7 +451,7 @@ __device__ __forceinline__ CflVal stage_cell(const StageArgs<T> &a, const int c)
         if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
             const T u = fdiv(nu, nh), v = fdiv(nv, nh);
             const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-            cfl = cfl_cell(a.cfl_rule, s, double(cg.y), double(lm));
+            cfl = cfl_cell<T>(a.cfl_rule, s, cg.y, lm);
         }
     }
     return cfl;
@@ -460,10 +463,10 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
     clock_upkeep(a);
     // one tile per block, or (persistent launch, gridDim < tiles) a
     // grid-stride sweep; either way each XCD takes contiguous tiles
-    __shared__ CflVal part[4];
+    __shared__ CflVal<T> part[4];
     const int ntiles = (a.n + (int)blockDim.x - 1) / (int)blockDim.x;
     for (int t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
-        const CflVal v = stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
+        const CflVal<T> v = stage_cell<T, SCHEME, LIM, WAFM>(a, t * (int)blockDim.x + (int)threadIdx.x);
         if (a.kind != 1) {
             cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, v, part);
             __syncthreads();  // part is reused by the next tile
@@ -480,12 +483,12 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 //     same tile is filed once, by the cell that is the L side of the
 //     canonical orientation; an edge to a cell outside the tile is filed by
 //     each side;
-//  2. the block runs the task lists densely (outside edges first: they also
-//     reconstruct the far side from its 2-ring; then inside edges, whose far
-//     side is already in LDS): hydrostatic reconstruction, HLLC in the
-//     canonical orientation, side corrections; each half-edge's share
-//     replaces its interface values in LDS (a slot is read and written by
-//     one task only);
+//  2. the block sweeps both task lists as one dense range (outside edges
+//     first: they also reconstruct the far side from its 2-ring; then inside
+//     edges, whose far side is already in LDS): hydrostatic reconstruction,
+//     HLLC in the canonical orientation, side corrections; each half-edge's
+//     share replaces its interface values in LDS (a slot is read and written
+//     by one task only);
 //  3. every thread sums its three half-edges weighted by L / area (plus the
 //     boundary fluxes), updates, applies Manning and the cleanup, and the
 //     block commits its CFL quantities.
@@ -508,7 +511,7 @@ k_stage_tiled(StageArgs<T> a)
     __shared__ T sB[3 * TILE];
     __shared__ unsigned short sTask[2][3 * TILE];
     __shared__ int sCount[2];
-    __shared__ CflVal sCfl[TILE / 64];
+    __shared__ CflVal<T> sCfl[TILE / 64];
     clock_upkeep(a);
     const T g = a.g, eps = a.eps;
     const int ntiles = (a.n + TILE - 1) / TILE;
@@ -558,12 +561,12 @@ k_stage_tiled(StageArgs<T> a)
             }
         }
         __syncthreads();
-        // ---- 2: edge tasks (outside-tile edges, then inside-tile edges)
-#pragma unroll
-        for (int list = 0; list < 2; ++list) {
-            const int nt = sCount[list];
+        // ---- 2: edge tasks, one dense sweep (outside-tile edges first)
+        {
+            const int n0 = sCount[0], nt = n0 + sCount[1];
             for (int i = threadIdx.x; i < nt; i += TILE) {
-                const int task = sTask[list][i];
+                const bool inside = i >= n0;
+                const int task = inside ? sTask[1][i - n0] : sTask[0][i];
                 const int tl = task >> 2, m = task & 3, tc = c0 + tl;
                 const int4 tn = a.nbr[tc];
                 const unsigned word = (unsigned)tn.w;
@@ -577,7 +580,7 @@ k_stage_tiled(StageArgs<T> a)
                 T4 kv;
                 T sbk = T(0);
                 int kl = -1;
-                if (list == 1) {
+                if (inside) {
                     kl = k - c0;
                     kv = sR[3 * kl + jb];
                     sbk = sB[3 * kl + jb];
@@ -624,7 +627,7 @@ k_stage_tiled(StageArgs<T> a)
                                fo.x, fo.y, fo.z);
                 fo.w = T(0);
                 sR[3 * tl + m] = fo;
-                if (list == 1) {  // the other cell's half-edge: normal -n, sign -sg
+                if (inside) {  // the other cell's half-edge: normal -n, sign -sg
                     T4 fk;
                     half_edge_flux(-sg, G0, G1, G2, T(0.5) * g * (kv.x * kv.x - hsk * hsk) + sbk, -nx,
                                    -ny, fk.x, fk.y, fk.z);
@@ -635,7 +638,7 @@ k_stage_tiled(StageArgs<T> a)
         }
         __syncthreads();
         // ---- 3: cell sums, update, friction, cleanup, CFL
-        CflVal cfl = cfl_none();
+        CflVal<T> cfl = cfl_none<T>();
         const int s = active ? (int)((unsigned)nb4.w >> kScenShift) : -1;
         const double dtd =
             wave_step_dt(a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl, a.dt_max, a.dt_fixed);
@@ -701,7 +704,7 @@ k_stage_tiled(StageArgs<T> a)
                 const T r = frcp(nh);
                 const T u = nu * r, v = nv * r;
                 const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-                cfl = cfl_cell(a.cfl_rule, s, double(cg.y), double(lm));
+                cfl = cfl_cell<T>(a.cfl_rule, s, cg.y, lm);
             }
         }
         if (a.kind != 1) cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, cfl, sCfl);
@@ -716,16 +719,16 @@ __global__ void __launch_bounds__(256) k_cfl_init(int n, const int4 *nbr,
                                                   const typename V4<T>::type *U, ClockWord *clock,
                                                   int ncopy, int slot, int rule, T g, T eps)
 {
-    __shared__ CflVal part[4];
+    __shared__ CflVal<T> part[4];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    CflVal v = cfl_none();
+    CflVal<T> v = cfl_none<T>();
     if (c < n) {
         const unsigned word = (unsigned)nbr[c].w;
         const T h = U[c].x;
         if (((word >> kOwnedBit) & 1u) && h > eps) {
             const T u = fdiv(U[c].y, h), w = fdiv(U[c].z, h);
             const T lm = sqrt(u * u + w * w) + sqrt(g * h);
-            v = cfl_cell(rule, (int)(word >> kScenShift), double(cell[c].y), double(lm));
+            v = cfl_cell<T>(rule, (int)(word >> kScenShift), cell[c].y, lm);
         }
         v.scen = (int)(word >> kScenShift);
     }
@@ -944,6 +947,7 @@ template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int
     if (scheme != kWAF && !cell) {
         if (block == 64) return pick_tiled<T, 64>(scheme, lim);
         if (block == 128) return pick_tiled<T, 128>(scheme, lim);
+        if (block == 512) return pick_tiled<T, 512>(scheme, lim);
         return pick_tiled<T, 256>(scheme, lim);
     }
     return pick_cell_kernel<T>(scheme, lim, wafm);
@@ -998,7 +1002,9 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.slot_reset = (int)((step + 2) % 3);
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, c->block,
                                    c->cfg.cell_kernel);
-    const int B = c->block;
+    // the one-thread-per-cell kernel is built for at most 256 threads
+    const bool cell_kernel = c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel;
+    const int B = cell_kernel ? std::min(c->block, 256) : c->block;
     const int ntiles = (c->n_total + B - 1) / B;
     const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
     const dim3 blk(B);
@@ -1083,7 +1089,8 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
-        !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) ||
+        !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+         cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1)
         return SWE_ERR_ARG;
     int ndev = 0;
@@ -1206,7 +1213,7 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     HIP_OK(c, hipMalloc(&c->phi, sizeof(float) * 3 * n));
     // CFL partial copies: enough lines that concurrent block commits rarely
     // meet on one, few enough that large batches stay small
-    c->ncopy = nm <= 64 ? 64 : (nm <= 1024 ? 16 : 4);
+    c->ncopy = nm <= 64 ? 16 : (nm <= 1024 ? 8 : 4);
     HIP_OK(c, hipMalloc(&c->clock, clock_bytes(c)));
     HIP_OK(c, hipMalloc(&c->t0, sizeof(double) * (size_t)nm));
     {
@@ -1464,7 +1471,8 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     const int cell0 = c->cfg.cell_kernel;
     int best_cell = cell0;
     for (int cellk = 0; cellk < (c->cfg.scheme == SWE_WAF ? 1 : 2); ++cellk)
-    for (int B : {64, 128, 256}) {
+    for (int B : {64, 128, 256, 512}) {
+        if (B == 512 && (cellk || c->cfg.scheme == SWE_WAF)) continue;  // tiled kernel only
         for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
             c->cfg.cell_kernel = c->cfg.scheme == SWE_WAF ? cell0 : cellk;
             c->block = B;

@@ -356,22 +356,19 @@ __device__ __forceinline__ Prim<T> prim(const T4 &U, T eps)
 }
 
 // beta limiters in branch-free form: zero unless both slopes have the same
-// sign, else the signed max(min(beta|sb|, |sf|), min(|sb|, beta|sf|)); this is
-// the printed MINBEE/SUPERBEE form of Sec. 6.2.3 value for value.
+// sign (their product is positive), else the signed
+// max(min(beta|sb|, |sf|), min(|sb|, beta|sf|)); this is the printed
+// MINBEE/SUPERBEE form of Sec. 6.2.3 value for value (but for slopes whose
+// product underflows, which count as zero).
 template <typename T, int LIM>
 __device__ __forceinline__ T limit2(T sb, T sf)
 {
-    if (LIM == kVanAlbada) {
-        const T p = sb * sf;
-        return p > T(0) ? p * (sb + sf) * frcp(sb * sb + sf * sf) : T(0);
-    }
     if (LIM == kZeroSlope) return T(0);
-    const bool same = (sb > T(0) && sf > T(0)) || (sb < T(0) && sf < T(0));
-    const T ab = sb < T(0) ? -sb : sb, af = sf < T(0) ? -sf : sf;
-    T m;
-    if (LIM == kSuperbee) m = tmax(tmin(T(2) * ab, af), tmin(ab, T(2) * af));
-    else m = tmin(ab, af);
-    return same ? (sf < T(0) ? -m : m) : T(0);
+    const T p = sb * sf;
+    if (LIM == kVanAlbada) return p > T(0) ? p * (sb + sf) * frcp(sb * sb + sf * sf) : T(0);
+    const T ab = fabs(sb), af = fabs(sf);
+    const T m = LIM == kSuperbee ? tmax(tmin(T(2) * ab, af), tmin(ab, T(2) * af)) : tmin(ab, af);
+    return p > T(0) ? copysign(m, sf) : T(0);
 }
 
 // Interface values of cell C across the edge with outward normal n (Sec.
@@ -449,19 +446,15 @@ __device__ __forceinline__ Half<T> recon3(const Prim<T> &C, const Prim<T> &K, co
     if ((ha && !(A.h > eps)) || (hb && !(B.h > eps)) || (!ha && !hb)) return r;
     const T qc[4] = {C.h, C.h + C.b, r.un, r.ut};
     const T qk[4] = {K.h, K.h + K.b, K.u * nx + K.v * ny, -K.u * ny + K.v * nx};
-    T qu[4];
-    if (ha && hb) {
-        qu[0] = T(0.5) * (A.h + B.h);
-        qu[1] = T(0.5) * ((A.h + A.b) + (B.h + B.b));
-        qu[2] = T(0.5) * ((A.u * nx + A.v * ny) + (B.u * nx + B.v * ny));
-        qu[3] = T(0.5) * ((-A.u * ny + A.v * nx) + (-B.u * ny + B.v * nx));
-    } else {
-        const Prim<T> &O = ha ? A : B;
-        qu[0] = O.h;
-        qu[1] = O.h + O.b;
-        qu[2] = O.u * nx + O.v * ny;
-        qu[3] = -O.u * ny + O.v * nx;
-    }
+    // upwind state: the mean of the upwind cells (rotation is linear, so the
+    // mean velocity is rotated once), or the one that exists
+    const bool both = ha && hb;
+    const Prim<T> &O = ha ? A : B;
+    const T uh = both ? T(0.5) * (A.h + B.h) : O.h;
+    const T ue = both ? T(0.5) * ((A.h + A.b) + (B.h + B.b)) : O.h + O.b;
+    const T uu = both ? T(0.5) * (A.u + B.u) : O.u;
+    const T uv = both ? T(0.5) * (A.v + B.v) : O.v;
+    const T qu[4] = {uh, ue, uu * nx + uv * ny, -uu * ny + uv * nx};
     T out[4];
     bool done = false;
     if (LIM == kLearned) {

@@ -40,7 +40,7 @@ def _batch(scs, steps, tune=False):
     s.set_state(h, hu, hv)
     if tune:
         b, g = s.autotune(5)
-        assert b in (64, 128, 256)
+        assert b in (64, 128, 256, 512)
         st = s.read_state()
         assert np.array_equal(st[0], h.astype(np.float32))
     s.step(steps)
