@@ -104,7 +104,7 @@ typedef struct {
     double eps;        /* wet/dry threshold [m], default 1e-6 */
     double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
     int block;         /* threads per block = cells per tile: 64, 128, 256 or 512 (0: 256);
-                          the one-thread-per-cell kernel uses at most 256 */
+                          the one-thread-per-cell kernel and FP64 use at most 256 */
     int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the
                           tiled kernel for HLLC1 and MUSCL (WAF always uses the cell kernel) */
     int reserved[6];

@@ -98,6 +98,64 @@ __device__ __forceinline__ double wave_step_dt(const ClockWord *clk, int ncopy, 
     return dt;
 }
 
+// The step in two halves, so that the latency of the clock lines (last
+// written by atomics of the previous kernel) hides behind the stencil work:
+// dt_prefetch loads, per lane, copy (lane mod ncopy) of the partials of the
+// scenario of the wave's first cell; dt_finish reduces them when the wave's
+// cells all belong to that scenario and otherwise falls back to
+// wave_step_dt.  Every lane of the wave calls both.
+struct DtPrefetch {
+    double mn, mx;
+    int S;
+};
+
+__device__ __forceinline__ DtPrefetch dt_prefetch(const ClockWord *clk, int ncopy, int slot,
+                                                  int s_own, double dt_fixed)
+{
+    DtPrefetch p;
+    const unsigned long long act = __ballot(s_own >= 0);
+    p.S = act ? __shfl(s_own, __builtin_ctzll(act)) : 0;
+    p.mn = 0.0;
+    p.mx = 0.0;
+    if (dt_fixed <= 0.0) {
+        const ClockWord *q = clk + clock_off(ncopy, p.S, slot) +
+                             (size_t)(1 + ((int)threadIdx.x & (ncopy - 1))) * kClockLine;
+        p.mn = bitsd(q[kCfqMin]);
+        p.mx = bitsd(q[kCfqMax]);
+    }
+    return p;
+}
+
+__device__ __forceinline__ double dt_finish(DtPrefetch p, const ClockWord *clk, int ncopy, int slot,
+                                            int s, int rule, double cfl, double dt_max,
+                                            double dt_fixed)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    if (__ballot(s >= 0 && s != p.S) != 0ull)
+        return wave_step_dt(clk, ncopy, slot, s, rule, cfl, dt_max, dt_fixed);
+    for (int o = ncopy >> 1; o > 0; o >>= 1) {
+        p.mn = fmin(p.mn, __shfl_xor(p.mn, o));
+        p.mx = fmax(p.mx, __shfl_xor(p.mx, o));
+    }
+    return s >= 0 ? cfl_dt(p.mn, p.mx, cfl, dt_max, rule) : 0.0;
+}
+
+// The same step as wave_step_dt for one lane on its own (copies reduced in
+// a loop; min and max are exact, so both agree bitwise).  For rare
+// divergent paths.
+__device__ __forceinline__ double lane_step_dt(const ClockWord *clk, int ncopy, int slot, int s,
+                                               int rule, double cfl, double dt_max, double dt_fixed)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    const ClockWord *q = clk + clock_off(ncopy, s, slot) + kClockLine;
+    double mn = bitsd(q[kCfqMin]), mx = bitsd(q[kCfqMax]);
+    for (int j = 1; j < ncopy; ++j) {
+        mn = fmin(mn, bitsd(q[(size_t)j * kClockLine + kCfqMin]));
+        mx = fmax(mx, bitsd(q[(size_t)j * kClockLine + kCfqMax]));
+    }
+    return cfl_dt(mn, mx, cfl, dt_max, rule);
+}
+
 // Per-cell CFL quantities (Sec. 6.2) of a wet owned cell, in the working
 // precision: mn = R_i / lambda_i (rule 0) or R_i (rule 1), mx = lambda_i;
 // neutral values otherwise.  They become doubles only when committed (the
@@ -273,6 +331,13 @@ __device__ __forceinline__ bool waf_upwind(const T4 &Ua, bool ha, const T4 &Ub, 
     return ha || hb;
 }
 
+// Component m (0..2) of an int4 by selects (no local array: a dynamically
+// indexed one lives in scratch memory).
+__device__ __forceinline__ int pick3(const int4 &v, int m)
+{
+    return m == 0 ? v.x : (m == 1 ? v.y : v.z);
+}
+
 // Clock upkeep of a stage kernel: the first kernel of a step clears the
 // partials of slot step + 2 (spread over the grid); the last one advances
 // each scenario's time by its step (wave 0 of block s mod grid).
@@ -356,8 +421,7 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
             bool hka = false, hkb = false;
             if (SCHEME != kHLLC1) {
                 const int4 nk = a.nbr[k];
-                const int nk3[3] = {nk.x, nk.y, nk.z};
-                const int ka = nk3[(jb + 1) % 3], kb = nk3[(jb + 2) % 3];
+                const int ka = pick3(nk, (jb + 1) % 3), kb = pick3(nk, (jb + 2) % 3);
                 hka = ka >= 0;
                 hkb = kb >= 0;
                 if (hka) Uka = a.Uin[ka];
@@ -489,15 +553,18 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 //     HLLC in the canonical orientation, side corrections; each half-edge's
 //     share replaces its interface values in LDS (a slot is read and written
 //     by one task only);
-//  3. every thread sums its three half-edges weighted by L / area (plus the
-//     boundary fluxes), updates, applies Manning and the cleanup, and the
-//     block commits its CFL quantities.
+//  3. every thread sums its three half-edge shares weighted by L / area,
+//     updates, applies Manning and the cleanup, and the block commits its
+//     CFL quantities.
+// Boundary half-edges are tasks of the first list too (their flux needs
+// only the cell's own state).
 // The flux of an edge is the same function of the same operands wherever it
 // is evaluated (operands selected, one evaluation, multiply-adds fused per
 // expression only), so results do not depend on the tiling (sub-domain runs
 // stay bitwise equal to undecomposed runs) and contributions cancel bitwise.
-// LDS per cell: 3 x (4 + 1) values + 3 16-bit task slots (18 KB per 256-cell
-// FP32 tile), so eight tiles fit a CU.
+// LDS per cell: 3 x (4 + 1) values, 3 task slots, 3 neighbour indices and
+// the word (22.5 KB per 256-cell FP32 tile, seven tiles per CU); phase 2
+// reads no global memory for edges inside the tile but the normal.
 #ifndef SWE_TILED_WAVES
 #define SWE_TILED_WAVES 6  // FP32: waves per SIMD the register budget is sized for
 #endif
@@ -506,10 +573,16 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(sizeo
 k_stage_tiled(StageArgs<T> a)
 {
     using T4 = typename V4<T>::type;
-    static_assert(4 * TILE <= 65536, "16-bit task entries");
+    static_assert(TILE <= 1024, "10-bit tile-local indices in task entries");
     __shared__ T4 sR[3 * TILE];
     __shared__ T sB[3 * TILE];
-    __shared__ unsigned short sTask[2][3 * TILE];
+    // tasks: outside-tile and boundary half-edges from the front, inside
+    // edges from the back; an entry packs m (2 bits), the filing cell (10),
+    // the neighbour's local edge jb (2), the L-side bit and, inside the
+    // tile, the neighbour's tile-local index (10)
+    __shared__ unsigned sTask[3 * TILE];
+    __shared__ int sK[3 * TILE];       // neighbour (or boundary tag) of each half-edge
+    __shared__ unsigned sW[TILE];      // packed word of each cell
     __shared__ int sCount[2];
     __shared__ CflVal<T> sCfl[TILE / 64];
     clock_upkeep(a);
@@ -521,13 +594,16 @@ k_stage_tiled(StageArgs<T> a)
         if (threadIdx.x < 2) sCount[threadIdx.x] = 0;
         __syncthreads();
         // ---- 1: primitives, own half-edges, task lists
+        DtPrefetch dtp;
         int4 nb4 = make_int4(-1, -1, -1, 0);
-        T4 Uc;
+        if (active) nb4 = a.nbr[c];
+        dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur, active ? (int)((unsigned)nb4.w >> kScenShift) : -1,
+                          a.dt_fixed);
         if (active) {
-            nb4 = a.nbr[c];
-            Uc = a.Uin[c];
+            const T4 Uc = a.Uin[c];
             const int nb[3] = {nb4.x, nb4.y, nb4.z};
             const unsigned word = (unsigned)nb4.w;
+            sW[cl] = word;
             const Prim<T> pc = prim(Uc, eps);
             Prim<T> pn[3];
             bool hn[3];
@@ -539,7 +615,13 @@ k_stage_tiled(StageArgs<T> a)
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const int k = nb[m];
-                if (k < 0) continue;  // boundary half-edge: phase 3
+                sK[3 * cl + m] = k;
+                const unsigned jb = (word >> (2 * m)) & 3u, isL = (word >> (6 + m)) & 1u;
+                const unsigned ent = (unsigned)m | ((unsigned)cl << 2) | (jb << 12) | (isL << 14);
+                if (k < 0) {  // boundary half-edge: a task of its own
+                    sTask[atomicAdd(&sCount[0], 1)] = ent;
+                    continue;
+                }
                 const T4 co = a.he_co[3 * c + m];
                 T ga = T(0);
                 float phi = 0.0f;
@@ -553,10 +635,9 @@ k_stage_tiled(StageArgs<T> a)
                 sB[3 * cl + m] = T(0.5) * g * (r.h + Uc.x) * (r.b - Uc.w);  // centred bed term
                 const int kl = k - c0;
                 if (kl >= 0 && kl < TILE) {
-                    if ((word >> (6 + m)) & 1u)
-                        sTask[1][atomicAdd(&sCount[1], 1)] = (unsigned short)(4 * cl + m);
+                    if (isL) sTask[3 * TILE - 1 - atomicAdd(&sCount[1], 1)] = ent | ((unsigned)kl << 15);
                 } else {
-                    sTask[0][atomicAdd(&sCount[0], 1)] = (unsigned short)(4 * cl + m);
+                    sTask[atomicAdd(&sCount[0], 1)] = ent;
                 }
             }
         }
@@ -566,22 +647,39 @@ k_stage_tiled(StageArgs<T> a)
             const int n0 = sCount[0], nt = n0 + sCount[1];
             for (int i = threadIdx.x; i < nt; i += TILE) {
                 const bool inside = i >= n0;
-                const int task = inside ? sTask[1][i - n0] : sTask[0][i];
-                const int tl = task >> 2, m = task & 3, tc = c0 + tl;
-                const int4 tn = a.nbr[tc];
-                const unsigned word = (unsigned)tn.w;
-                const int k = m == 0 ? tn.x : (m == 1 ? tn.y : tn.z);
-                const int jb = (word >> (2 * m)) & 3;
-                const bool isL = (word >> (6 + m)) & 1u;
+                const unsigned task = inside ? sTask[3 * TILE - 1 - (i - n0)] : sTask[i];
+                const int m = task & 3u, tl = (task >> 2) & 1023u, jb = (task >> 12) & 3u;
+                const bool isL = (task >> 14) & 1u;
+                const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
+                const int tc = c0 + tl;
+                const int k = inside ? c0 + kl : sK[3 * tl + m];
                 const T4 co = a.he_co[3 * tc + m];
                 const T nx = co.x, ny = co.y;
+                if (k < 0) {  // boundary flux (Sec. 6.1), in the global frame
+                    const T4 Ut = a.Uin[tc];
+                    const int st = (int)(sW[tl] >> kScenShift);
+                    const ScenParams sp = a.scen[st];
+                    T q_in = T(0);
+                    if (k == kBcInflow) {
+                        const double t_st =
+                            bitsd(a.clock[clock_off(a.ncopy, st, a.slot_cur)]) +
+                            (a.kind == 2 ? lane_step_dt(a.clock, a.ncopy, a.slot_cur, st, a.cfl_rule,
+                                                        a.cfl, a.dt_max, a.dt_fixed)
+                                         : 0.0);
+                        q_in = T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len);
+                    }
+                    T G[3];
+                    boundary_flux<T, T4>(k, Ut, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
+                    T4 fb;
+                    fb.x = G[0]; fb.y = G[1]; fb.z = G[2]; fb.w = T(0);
+                    sR[3 * tl + m] = fb;
+                    continue;
+                }
                 const T4 ov = sR[3 * tl + m];
                 const T sbo = sB[3 * tl + m];
                 T4 kv;
                 T sbk = T(0);
-                int kl = -1;
                 if (inside) {
-                    kl = k - c0;
                     kv = sR[3 * kl + jb];
                     sbk = sB[3 * kl + jb];
                 } else {
@@ -594,8 +692,7 @@ k_stage_tiled(StageArgs<T> a)
                     float phik = 0.0f;
                     if (MUSCL_) {
                         const int4 nk = a.nbr[k];
-                        const int nk3[3] = {nk.x, nk.y, nk.z};
-                        const int ka = nk3[(jb + 1) % 3], kb = nk3[(jb + 2) % 3];
+                        const int ka = pick3(nk, (jb + 1) % 3), kb = pick3(nk, (jb + 2) % 3);
                         hka = ka >= 0;
                         hkb = kb >= 0;
                         if (hka) pka = prim(a.Uin[ka], eps);
@@ -638,37 +735,28 @@ k_stage_tiled(StageArgs<T> a)
         }
         __syncthreads();
         // ---- 3: cell sums, update, friction, cleanup, CFL
+        // the cell's state is read again (a cache hit) rather than held in
+        // registers across phase 2
         CflVal<T> cfl = cfl_none<T>();
-        const int s = active ? (int)((unsigned)nb4.w >> kScenShift) : -1;
-        const double dtd =
-            wave_step_dt(a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl, a.dt_max, a.dt_fixed);
+        T4 Uc;
+        unsigned word = 0u;
         if (active) {
-            const unsigned word = (unsigned)nb4.w;
+            Uc = a.Uin[c];
+            word = sW[cl];
+        }
+        const int s = active ? (int)(word >> kScenShift) : -1;
+        const double dtd = dt_finish(dtp, a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl,
+                                     a.dt_max, a.dt_fixed);
+        if (active) {
             const T dt = T(dtd);
-            const int nb[3] = {nb4.x, nb4.y, nb4.z};
             T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const T lam = a.he_lam[3 * c + m];
-                if (nb[m] < 0) {
-                    const T4 co = a.he_co[3 * c + m];
-                    const ScenParams sp = a.scen[s];
-                    const double t_st = bitsd(a.clock[clock_off(a.ncopy, s, a.slot_cur)]) +
-                                        (a.kind == 2 ? dtd : 0.0);
-                    const T q_in = nb[m] == kBcInflow
-                                       ? T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len)
-                                       : T(0);
-                    T G[3];
-                    boundary_flux<T, T4>(nb[m], Uc, co.x, co.y, g, eps, q_in, T(sp.outflow_stage), G);
-                    acc0 += lam * G[0];
-                    acc1 += lam * G[1];
-                    acc2 += lam * G[2];
-                } else {
-                    const T4 f = sR[3 * cl + m];
-                    acc0 += lam * f.x;
-                    acc1 += lam * f.y;
-                    acc2 += lam * f.z;
-                }
+                const T4 f = sR[3 * cl + m];
+                acc0 += lam * f.x;
+                acc1 += lam * f.y;
+                acc2 += lam * f.z;
             }
             T nh = Uc.x - dt * acc0;
             T nu = Uc.y - dt * acc1;
@@ -708,7 +796,7 @@ k_stage_tiled(StageArgs<T> a)
             }
         }
         if (a.kind != 1) cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, cfl, sCfl);
-        __syncthreads();  // LDS is reused by the next tile
+        if (tile + (int)gridDim.x < ntiles) __syncthreads();  // LDS is reused by the next tile
     }
 }
 
@@ -947,7 +1035,7 @@ template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int
     if (scheme != kWAF && !cell) {
         if (block == 64) return pick_tiled<T, 64>(scheme, lim);
         if (block == 128) return pick_tiled<T, 128>(scheme, lim);
-        if (block == 512) return pick_tiled<T, 512>(scheme, lim);
+        if (block == 512 && sizeof(T) == 4) return pick_tiled<T, 512>(scheme, lim);
         return pick_tiled<T, 256>(scheme, lim);
     }
     return pick_cell_kernel<T>(scheme, lim, wafm);
@@ -1000,11 +1088,12 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.slot_cur = (int)(step % 3);
     a.slot_next = (int)((step + 1) % 3);
     a.slot_reset = (int)((step + 2) % 3);
-    KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, c->block,
-                                   c->cfg.cell_kernel);
-    // the one-thread-per-cell kernel is built for at most 256 threads
+    // the one-thread-per-cell kernel is built for at most 256 threads, and
+    // FP64 tiles stop at 256 cells (LDS)
     const bool cell_kernel = c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel;
-    const int B = cell_kernel ? std::min(c->block, 256) : c->block;
+    const int B = cell_kernel || sizeof(T) == 8 ? std::min(c->block, 256) : c->block;
+    KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B,
+                                   c->cfg.cell_kernel);
     const int ntiles = (c->n_total + B - 1) / B;
     const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
     const dim3 blk(B);
