@@ -261,8 +261,10 @@ template <typename T> struct StageArgs {
     int n, n_scen;
     const int4 *nbr;
     const T4 *cell, *he_geo, *he_dist;
-    const T4 *he_co;             // per half-edge: nx, ny, d_mid / d_up, d_mid / d_fwd
-    const T *he_lam, *he_gam;    // per half-edge: L / area, d_mid / d_central
+    // per half-edge, edge-major (m * n + c): nx, ny, d_mid / d_up, d_mid / d_fwd;
+    // L / area; d_mid / d_central
+    const T4 *he_co;
+    const T *he_lam, *he_gam;
     const T4 *Uin, *U0;
     T4 *Uout;
     ClockWord *clock;
@@ -564,7 +566,9 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 // stay bitwise equal to undecomposed runs) and contributions cancel bitwise.
 // LDS per cell: 3 x (4 + 1) values, 3 task slots, 3 neighbour indices and
 // the word (22.5 KB per 256-cell FP32 tile, seven tiles per CU); phase 2
-// reads no global memory for edges inside the tile but the normal.
+// reads no global memory for edges inside the tile but the normal.  Half-edge
+// slots are local-edge-major (slot of cell l, edge m at m * TILE + l), so a
+// wave's per-cell accesses are consecutive.
 #ifndef SWE_TILED_WAVES
 #define SWE_TILED_WAVES 6  // FP32: waves per SIMD the register budget is sized for
 #endif
@@ -615,24 +619,24 @@ k_stage_tiled(StageArgs<T> a)
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const int k = nb[m];
-                sK[3 * cl + m] = k;
+                sK[m * TILE + cl] = k;
                 const unsigned jb = (word >> (2 * m)) & 3u, isL = (word >> (6 + m)) & 1u;
                 const unsigned ent = (unsigned)m | ((unsigned)cl << 2) | (jb << 12) | (isL << 14);
                 if (k < 0) {  // boundary half-edge: a task of its own
                     sTask[atomicAdd(&sCount[0], 1)] = ent;
                     continue;
                 }
-                const T4 co = a.he_co[3 * c + m];
+                const T4 co = a.he_co[m * a.n + c];
                 T ga = T(0);
                 float phi = 0.0f;
-                if (MUSCL_ && LIM == kLearned) { ga = a.he_gam[3 * c + m]; phi = a.phi[3 * c + m]; }
+                if (MUSCL_ && LIM == kLearned) { ga = a.he_gam[m * a.n + c]; phi = a.phi[3 * c + m]; }
                 const int ma = (m + 1) % 3, mb = (m + 2) % 3;
                 const Half<T> r = recon3<T, MUSCL_, LIM>(pc, pn[m], pn[ma], hn[ma], pn[mb], hn[mb],
                                                           co.x, co.y, co.z, co.w, ga, phi, eps);
                 T4 rv;
                 rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
-                sR[3 * cl + m] = rv;
-                sB[3 * cl + m] = T(0.5) * g * (r.h + Uc.x) * (r.b - Uc.w);  // centred bed term
+                sR[m * TILE + cl] = rv;
+                sB[m * TILE + cl] = T(0.5) * g * (r.h + Uc.x) * (r.b - Uc.w);  // centred bed term
                 const int kl = k - c0;
                 if (kl >= 0 && kl < TILE) {
                     if (isL) sTask[3 * TILE - 1 - atomicAdd(&sCount[1], 1)] = ent | ((unsigned)kl << 15);
@@ -652,8 +656,8 @@ k_stage_tiled(StageArgs<T> a)
                 const bool isL = (task >> 14) & 1u;
                 const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
                 const int tc = c0 + tl;
-                const int k = inside ? c0 + kl : sK[3 * tl + m];
-                const T4 co = a.he_co[3 * tc + m];
+                const int k = inside ? c0 + kl : sK[m * TILE + tl];
+                const T4 co = a.he_co[m * a.n + tc];
                 const T nx = co.x, ny = co.y;
                 if (k < 0) {  // boundary flux (Sec. 6.1), in the global frame
                     const T4 Ut = a.Uin[tc];
@@ -672,16 +676,16 @@ k_stage_tiled(StageArgs<T> a)
                     boundary_flux<T, T4>(k, Ut, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
                     T4 fb;
                     fb.x = G[0]; fb.y = G[1]; fb.z = G[2]; fb.w = T(0);
-                    sR[3 * tl + m] = fb;
+                    sR[m * TILE + tl] = fb;
                     continue;
                 }
-                const T4 ov = sR[3 * tl + m];
-                const T sbo = sB[3 * tl + m];
+                const T4 ov = sR[m * TILE + tl];
+                const T sbo = sB[m * TILE + tl];
                 T4 kv;
                 T sbk = T(0);
                 if (inside) {
-                    kv = sR[3 * kl + jb];
-                    sbk = sB[3 * kl + jb];
+                    kv = sR[jb * TILE + kl];
+                    sbk = sB[jb * TILE + kl];
                 } else {
                     // far side: its own reconstruction across this edge, from its 2-ring
                     const Prim<T> pk = prim(a.Uin[k], eps);
@@ -697,10 +701,10 @@ k_stage_tiled(StageArgs<T> a)
                         hkb = kb >= 0;
                         if (hka) pka = prim(a.Uin[ka], eps);
                         if (hkb) pkb = prim(a.Uin[kb], eps);
-                        const T4 ck = a.he_co[3 * k + jb];
+                        const T4 ck = a.he_co[jb * a.n + k];
                         al = ck.z;
                         be = ck.w;
-                        if (LIM == kLearned) { ga = a.he_gam[3 * k + jb]; phik = a.phi[3 * k + jb]; }
+                        if (LIM == kLearned) { ga = a.he_gam[jb * a.n + k]; phik = a.phi[3 * k + jb]; }
                     }
                     const Half<T> r = recon3<T, MUSCL_, LIM>(pk, pc, pka, hka, pkb, hkb, -nx, -ny, al,
                                                               be, ga, phik, eps);
@@ -723,13 +727,13 @@ k_stage_tiled(StageArgs<T> a)
                 half_edge_flux(sg, G0, G1, G2, T(0.5) * g * (ov.x * ov.x - hso * hso) + sbo, nx, ny,
                                fo.x, fo.y, fo.z);
                 fo.w = T(0);
-                sR[3 * tl + m] = fo;
+                sR[m * TILE + tl] = fo;
                 if (inside) {  // the other cell's half-edge: normal -n, sign -sg
                     T4 fk;
                     half_edge_flux(-sg, G0, G1, G2, T(0.5) * g * (kv.x * kv.x - hsk * hsk) + sbk, -nx,
                                    -ny, fk.x, fk.y, fk.z);
                     fk.w = T(0);
-                    sR[3 * kl + jb] = fk;
+                    sR[jb * TILE + kl] = fk;
                 }
             }
         }
@@ -752,8 +756,8 @@ k_stage_tiled(StageArgs<T> a)
             T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const T lam = a.he_lam[3 * c + m];
-                const T4 f = sR[3 * cl + m];
+                const T lam = a.he_lam[m * a.n + c];
+                const T4 f = sR[m * TILE + cl];
                 acc0 += lam * f.x;
                 acc1 += lam * f.y;
                 acc2 += lam * f.z;
@@ -965,16 +969,20 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
     // are positively homogeneous of degree one, so d_mid * lim(sb, sf) =
     // lim(d_mid sb, d_mid sf)), the learned limiter's central weight and the
     // edge length over the cell area
+    // Stored edge-major (half-edge m of cell c at m * n + c), so that a
+    // wave's loads of one local edge are contiguous.
     std::vector<T> co(12 * n), lam(3 * n), gam(3 * n);
-    for (size_t h = 0; h < 3 * n; ++h) {
-        const double *ge = &g.he_geo[4 * h], *gd = &g.he_dist[4 * h];
-        co[4 * h + 0] = T(ge[0]);
-        co[4 * h + 1] = T(ge[1]);
-        co[4 * h + 2] = T(ge[3] * gd[0]);
-        co[4 * h + 3] = T(ge[3] * gd[1]);
-        lam[h] = T(ge[2] * g.cell[4 * (h / 3)]);
-        gam[h] = T(ge[3] * gd[2]);
-    }
+    for (size_t cc = 0; cc < n; ++cc)
+        for (size_t m = 0; m < 3; ++m) {
+            const size_t h = 3 * cc + m, e = m * n + cc;
+            const double *ge = &g.he_geo[4 * h], *gd = &g.he_dist[4 * h];
+            co[4 * e + 0] = T(ge[0]);
+            co[4 * e + 1] = T(ge[1]);
+            co[4 * e + 2] = T(ge[3] * gd[0]);
+            co[4 * e + 3] = T(ge[3] * gd[1]);
+            lam[e] = T(ge[2] * g.cell[4 * cc]);
+            gam[e] = T(ge[3] * gd[2]);
+        }
     HIP_OK(c, hipMalloc(&c->he_co, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_co, co.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
     HIP_OK(c, hipMalloc(&c->he_lam, 3 * sizeof(T) * n));

@@ -184,16 +184,18 @@ def test_bad_state_and_mesh_rejected():
     assert e.value.code == -2
 
 
-def test_full_config2_ten_steps_fp32():
+def test_full_config2_fp32():
     """Config 2 at full size (999,824 cells) in the launch configuration the
-    benchmark times: 10 fixed-dt MUSCL-HLLC-RK2 steps against the oracle on
-    every cell."""
+    benchmark times: 100 fixed-dt MUSCL-HLLC-RK2 steps (the inflow front has
+    entered; after only a few steps hv is round-off of a lake at rest and the
+    relative metric measures noise over a near-zero field) against the
+    oracle on every cell."""
     from swe_inputs import config2
     sc = config2()
     s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=0)
     l2g = pr.sub.l2g
     dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
-    g, r = _run_both(s, M, par, sc, l2g, 10, dt_fixed=dt)
+    g, r = _run_both(s, M, par, sc, l2g, 100, dt_fixed=dt)
     errs = state_errors(g, r[:3], pr.sub.n_owned)
-    print("config2 full, 10 steps", errs)
+    print("config2 full, 100 steps", errs)
     assert max(errs) <= 1e-4, errs
