@@ -94,13 +94,15 @@ def measured_traffic(workload_name):
         return None
 
 
-def cpu_baseline(sc, kw, seconds):
+def cpu_baseline(sc, kw, seconds, mlp=None):
     """Serial FP64 oracle on the same mesh: as many steps as fit in about
     ``seconds`` (at least one), one core."""
     from oracle import oracle as O
     M, _ = O.global_mesh(sc)
     p = O.scenario_params(sc, scheme=kw["scheme"], integrator=kw["integrator"],
                           limiter=kw["limiter"])
+    if mlp is not None:
+        p.mlp = mlp
     h, hu, hv, t = sc.h, sc.hu, sc.hv, 0.0
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -125,6 +127,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cell-kernel", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--limiter", choices=("minmod", "learned"), default="minmod",
+                    help="learned: the per-edge network (untrained weights: its cost, not its "
+                         "accuracy) ahead of every stage")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for the HBM byte counters)")
@@ -149,7 +154,14 @@ def main():
     from paper_2307_16758_amd.problem import prepare_scenario
 
     sc, kw, P, k = workload(args.workload)
+    if args.limiter == "learned":
+        kw = dict(kw, limiter=swe.LEARNED)
     s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel, **kw)
+    mlp = None
+    if args.limiter == "learned":
+        from paper_2307_16758_amd.limiter_train import init_params
+        mlp = init_params()
+        s.limiter_set_weights(mlp)
     sendbuf = None
     if isinstance(sc, list):                      # batched ensemble
         preps = [prepare_scenario(x) for x in sc]
@@ -231,6 +243,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
                                f"{'MUSCL-HLLC-RK2' if rk2 else 'HLLC-Euler'}"
+                               + (", learned limiter" if args.limiter == "learned" else "")
                                + (f", part of {P} with {k} ghost layers + pack" if P > 1 else ""),
                    "cells": n_owned, "tuned_launch": tuned,
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
@@ -245,7 +258,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc[0] if isinstance(sc, list) else sc, kw,
-                                           args.cpu_seconds)
+                                           args.cpu_seconds, mlp)
     print(json.dumps(out), flush=True)
 
 

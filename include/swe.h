@@ -146,7 +146,9 @@ const char *swe_strerror(int code);
 /* Copy a mesh to the device: validation (counter-clockwise cells, symmetric
  * neighbours, ghost and send ranges in bounds), geometry (areas, normals,
  * lengths, inscribed radii, MUSCL distances) and the device layout.
- * Replaces any previous mesh; the state must be set again afterwards. */
+ * Replaces any previous mesh; the state must be set again afterwards.
+ * SWE_ERR_UNSUPPORTED when a per-cell array would exceed 4 GiB (more than
+ * about 89 million cells in FP32, 44 million in FP64, per context). */
 int swe_mesh_upload(swe_ctx *ctx, const swe_mesh *mesh);
 
 /* Inflow hydrograph Q(t), piecewise linear through n points (clamped at the
@@ -172,11 +174,12 @@ int swe_set_bc_series_scenario(swe_ctx *ctx, int scenario, int n, const double *
 int swe_batch_offsets(const swe_ctx *ctx, int32_t *n_scenarios, int32_t *offsets);
 int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
 
-/* Autotuner: times n_steps CFL steps for each launch shape (tiled or cell
- * kernel; 64, 128, 256 or 512 (tiled only) threads per block; one tile per block or a
- * persistent grid of 2048 / block blocks per compute unit) from the current
- * state, keeps the fastest and restores the state, clocks and time.  The
- * choice never changes results (every variant computes the same values).
+/* Autotuner: times n_steps CFL steps for each launch shape of the
+ * configured stage kernel (64, 128, 256 or, FP32 tiled kernel only, 512
+ * threads per block; one tile per block or a persistent grid of
+ * 2048 / block blocks per compute unit) from the current state, keeps the
+ * fastest and restores the state, clocks and time.  The choice never
+ * changes results (the tiled kernel is bitwise independent of the tiling).
  * Outputs may be NULL. */
 int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
 

@@ -6,10 +6,11 @@
 // first), so a block's 1- and 2-ring gathers stay in the XCD's L2; blocks are
 // remapped so that each of the 8 XCDs sweeps one contiguous range of tiles.
 // Every interior edge flux is evaluated in the canonical orientation (L = the
-// cell of smaller global id, L's normal) by both of its cells with identical
-// operands, so the two contributions cancel bitwise; cell sums run over the
-// local edges 0, 1, 2 in order; there are no atomics on the state, and the
-// results are deterministic run to run.
+// cell of smaller global id, L's normal) from identical operands wherever it
+// is evaluated, so the two mass contributions cancel bitwise and results do
+// not depend on the tiling; cell sums run over the local edges 0, 1, 2 in
+// order; there are no atomics on the state, and the results are
+// deterministic run to run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -306,6 +307,31 @@ __device__ __forceinline__ void boundary_flux(int tag, const T4 &Uc, T nx, T ny,
     G[2] = F[1] * ny + F[2] * nx;
 }
 
+// Boundary flux of Sec. 6.1 in the global frame, less the hydrostatic
+// pressure g h^2 / 2 of the cell along the normal (the pressure-deviation
+// form of the tiled kernel): a wall then contributes nothing.
+template <typename T, typename T4>
+__device__ __forceinline__ void boundary_flux_dev(int tag, const T4 &Uc, T nx, T ny, T g, T eps,
+                                                  T q_in, T stage, T G[3])
+{
+    const T h = Uc.x;
+    T F0 = T(0), D = T(0), F2 = T(0);
+    if (tag == kBcInflow) {
+        const T hl = tmax(h, T(1e-3));
+        F0 = -q_in;
+        D = fdiv(q_in * q_in, hl);
+    } else if (tag != kBcWall) {
+        const T r = h > eps ? frcp(h) : T(0);
+        const T un = (Uc.y * nx + Uc.z * ny) * r, ut = (-Uc.y * ny + Uc.z * nx) * r;
+        const T hg = tag == kBcOutflow ? tmax(T(0), stage - Uc.w) : h;
+        T DR;
+        hllc_dev(g, eps, h, un, ut, hg, un, ut, F0, D, DR, F2);
+    }
+    G[0] = F0;
+    G[1] = D * nx - F2 * ny;
+    G[2] = D * ny + F2 * nx;
+}
+
 template <typename T, typename T4>
 __device__ __forceinline__ T tangential(const T4 &U, T nx, T ny, T eps)
 {
@@ -331,6 +357,18 @@ __device__ __forceinline__ bool waf_upwind(const T4 &Ua, bool ha, const T4 &Ub, 
         e = T(0); v = T(0);
     }
     return ha || hb;
+}
+
+// Element i of an array addressed with a 32-bit byte offset from a uniform
+// base (the arrays of a context stay below 4 GiB, checked at upload), so
+// the load takes one offset register and no 64-bit address arithmetic.
+template <typename V> __device__ __forceinline__ V ldx(const V *base, unsigned i)
+{
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + i * (unsigned)sizeof(V));
+}
+template <typename V> __device__ __forceinline__ void stx(V *base, unsigned i, const V &v)
+{
+    *reinterpret_cast<V *>(reinterpret_cast<char *>(base) + i * (unsigned)sizeof(V)) = v;
 }
 
 // Component m (0..2) of an int4 by selects (no local array: a dynamically
@@ -563,7 +601,14 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 // The flux of an edge is the same function of the same operands wherever it
 // is evaluated (operands selected, one evaluation, multiply-adds fused per
 // expression only), so results do not depend on the tiling (sub-domain runs
-// stay bitwise equal to undecomposed runs) and contributions cancel bitwise.
+// stay bitwise equal to undecomposed runs) and mass contributions cancel
+// bitwise.  Momentum is summed in pressure-deviation form: every share of a
+// cell is taken less the cell's own hydrostatic pressure g h^2 / 2 along its
+// normal, which changes nothing exactly (the outward normals of a triangle
+// times its edge lengths sum to zero) but makes a lake at rest exactly at
+// rest in floating point and removes the rounding of the large cancelling
+// pressure terms (Sec. 6.2.3's side corrections and centred bed term become
+// g (h- + h)(eta- - eta) / 2; hllc_dev gives F1 - g h*^2 / 2 per side).
 // LDS per cell: 3 x (4 + 1) values, 3 task slots, 3 neighbour indices and
 // the word (22.5 KB per 256-cell FP32 tile, seven tiles per CU); phase 2
 // reads no global memory for edges inside the tile but the normal.  Half-edge
@@ -600,11 +645,11 @@ k_stage_tiled(StageArgs<T> a)
         // ---- 1: primitives, own half-edges, task lists
         DtPrefetch dtp;
         int4 nb4 = make_int4(-1, -1, -1, 0);
-        if (active) nb4 = a.nbr[c];
+        if (active) nb4 = ldx(a.nbr, c);
         dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur, active ? (int)((unsigned)nb4.w >> kScenShift) : -1,
                           a.dt_fixed);
         if (active) {
-            const T4 Uc = a.Uin[c];
+            const T4 Uc = ldx(a.Uin, c);
             const int nb[3] = {nb4.x, nb4.y, nb4.z};
             const unsigned word = (unsigned)nb4.w;
             sW[cl] = word;
@@ -626,17 +671,19 @@ k_stage_tiled(StageArgs<T> a)
                     sTask[atomicAdd(&sCount[0], 1)] = ent;
                     continue;
                 }
-                const T4 co = a.he_co[m * a.n + c];
+                const T4 co = ldx(a.he_co, m * a.n + c);
                 T ga = T(0);
                 float phi = 0.0f;
-                if (MUSCL_ && LIM == kLearned) { ga = a.he_gam[m * a.n + c]; phi = a.phi[3 * c + m]; }
+                if (MUSCL_ && LIM == kLearned) { ga = ldx(a.he_gam, m * a.n + c); phi = ldx(a.phi, 3 * c + m); }
                 const int ma = (m + 1) % 3, mb = (m + 2) % 3;
                 const Half<T> r = recon3<T, MUSCL_, LIM>(pc, pn[m], pn[ma], hn[ma], pn[mb], hn[mb],
                                                           co.x, co.y, co.z, co.w, ga, phi, eps);
                 T4 rv;
                 rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
                 sR[m * TILE + cl] = rv;
-                sB[m * TILE + cl] = T(0.5) * g * (r.h + Uc.x) * (r.b - Uc.w);  // centred bed term
+                // side correction and centred bed term less the cell's
+                // hydrostatic pressure: g (h- + h)(eta- - eta) / 2 along n
+                sB[m * TILE + cl] = T(0.5) * g * (r.h + Uc.x) * (r.eta - (pc.h + pc.b));
                 const int kl = k - c0;
                 if (kl >= 0 && kl < TILE) {
                     if (isL) sTask[3 * TILE - 1 - atomicAdd(&sCount[1], 1)] = ent | ((unsigned)kl << 15);
@@ -657,10 +704,10 @@ k_stage_tiled(StageArgs<T> a)
                 const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
                 const int tc = c0 + tl;
                 const int k = inside ? c0 + kl : sK[m * TILE + tl];
-                const T4 co = a.he_co[m * a.n + tc];
+                const T4 co = ldx(a.he_co, m * a.n + tc);
                 const T nx = co.x, ny = co.y;
                 if (k < 0) {  // boundary flux (Sec. 6.1), in the global frame
-                    const T4 Ut = a.Uin[tc];
+                    const T4 Ut = ldx(a.Uin, tc);
                     const int st = (int)(sW[tl] >> kScenShift);
                     const ScenParams sp = a.scen[st];
                     T q_in = T(0);
@@ -673,7 +720,7 @@ k_stage_tiled(StageArgs<T> a)
                         q_in = T(inflow_at(sp, a.ser_t, a.ser_q, t_st) * sp.inv_inflow_len);
                     }
                     T G[3];
-                    boundary_flux<T, T4>(k, Ut, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
+                    boundary_flux_dev<T, T4>(k, Ut, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
                     T4 fb;
                     fb.x = G[0]; fb.y = G[1]; fb.z = G[2]; fb.w = T(0);
                     sR[m * TILE + tl] = fb;
@@ -688,23 +735,23 @@ k_stage_tiled(StageArgs<T> a)
                     sbk = sB[jb * TILE + kl];
                 } else {
                     // far side: its own reconstruction across this edge, from its 2-ring
-                    const Prim<T> pk = prim(a.Uin[k], eps);
-                    const Prim<T> pc = prim(a.Uin[tc], eps);
+                    const Prim<T> pk = prim(ldx(a.Uin, k), eps);
+                    const Prim<T> pc = prim(ldx(a.Uin, tc), eps);
                     Prim<T> pka = pk, pkb = pk;
                     bool hka = false, hkb = false;
                     T al = T(0), be = T(0), ga = T(0);
                     float phik = 0.0f;
                     if (MUSCL_) {
-                        const int4 nk = a.nbr[k];
+                        const int4 nk = ldx(a.nbr, k);
                         const int ka = pick3(nk, (jb + 1) % 3), kb = pick3(nk, (jb + 2) % 3);
                         hka = ka >= 0;
                         hkb = kb >= 0;
-                        if (hka) pka = prim(a.Uin[ka], eps);
-                        if (hkb) pkb = prim(a.Uin[kb], eps);
-                        const T4 ck = a.he_co[jb * a.n + k];
+                        if (hka) pka = prim(ldx(a.Uin, ka), eps);
+                        if (hkb) pkb = prim(ldx(a.Uin, kb), eps);
+                        const T4 ck = ldx(a.he_co, jb * a.n + k);
                         al = ck.z;
                         be = ck.w;
-                        if (LIM == kLearned) { ga = a.he_gam[jb * a.n + k]; phik = a.phi[3 * k + jb]; }
+                        if (LIM == kLearned) { ga = ldx(a.he_gam, jb * a.n + k); phik = ldx(a.phi, 3 * k + jb); }
                     }
                     const Half<T> r = recon3<T, MUSCL_, LIM>(pk, pc, pka, hka, pkb, hkb, -nx, -ny, al,
                                                               be, ga, phik, eps);
@@ -719,19 +766,22 @@ k_stage_tiled(StageArgs<T> a)
                 const T hL = isL ? hso : hsk, uL = isL ? ov.z : kv.z, vL = isL ? ov.w : kv.w;
                 const T hR = isL ? hsk : hso, uR = isL ? -kv.z : -ov.z, vR = isL ? -kv.w : -ov.w;
                 const T nLx = isL ? nx : -nx, nLy = isL ? ny : -ny;
-                T F[3];
-                hllc_prim(g, eps, hL, uL, vL, hR, uR, vR, F);
-                const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
+                T F0, DL, DR, F2;
+                hllc_dev(g, eps, hL, uL, vL, hR, uR, vR, F0, DL, DR, F2);
                 const T sg = isL ? T(1) : T(-1);
+                // each side's normal momentum flux less its own hydrostatic
+                // pressure, rotated back from the canonical frame
+                const T Do = isL ? DL : DR;
                 T4 fo;
-                half_edge_flux(sg, G0, G1, G2, T(0.5) * g * (ov.x * ov.x - hso * hso) + sbo, nx, ny,
-                               fo.x, fo.y, fo.z);
+                half_edge_flux(sg, F0, Do * nLx - F2 * nLy, Do * nLy + F2 * nLx, sbo, nx, ny, fo.x,
+                               fo.y, fo.z);
                 fo.w = T(0);
                 sR[m * TILE + tl] = fo;
                 if (inside) {  // the other cell's half-edge: normal -n, sign -sg
+                    const T Dk = isL ? DR : DL;
                     T4 fk;
-                    half_edge_flux(-sg, G0, G1, G2, T(0.5) * g * (kv.x * kv.x - hsk * hsk) + sbk, -nx,
-                                   -ny, fk.x, fk.y, fk.z);
+                    half_edge_flux(-sg, F0, Dk * nLx - F2 * nLy, Dk * nLy + F2 * nLx, sbk, -nx, -ny,
+                                   fk.x, fk.y, fk.z);
                     fk.w = T(0);
                     sR[jb * TILE + kl] = fk;
                 }
@@ -745,7 +795,7 @@ k_stage_tiled(StageArgs<T> a)
         T4 Uc;
         unsigned word = 0u;
         if (active) {
-            Uc = a.Uin[c];
+            Uc = ldx(a.Uin, c);
             word = sW[cl];
         }
         const int s = active ? (int)(word >> kScenShift) : -1;
@@ -756,7 +806,7 @@ k_stage_tiled(StageArgs<T> a)
             T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const T lam = a.he_lam[m * a.n + c];
+                const T lam = ldx(a.he_lam, m * a.n + c);
                 const T4 f = sR[m * TILE + cl];
                 acc0 += lam * f.x;
                 acc1 += lam * f.y;
@@ -765,7 +815,7 @@ k_stage_tiled(StageArgs<T> a)
             T nh = Uc.x - dt * acc0;
             T nu = Uc.y - dt * acc1;
             T nv = Uc.z - dt * acc2;
-            const T4 cg = a.cell[c];
+            const T4 cg = ldx(a.cell, c);
             int flags = 0;
             if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
             if (nh < T(0)) {
@@ -781,7 +831,7 @@ k_stage_tiled(StageArgs<T> a)
                 nu *= rf; nv *= rf;
             }
             if (a.kind == 2) {
-                const T4 U0c = a.U0[c];
+                const T4 U0c = ldx(a.U0, c);
                 nh = T(0.5) * (U0c.x + nh);
                 nu = T(0.5) * (U0c.y + nu);
                 nv = T(0.5) * (U0c.z + nv);
@@ -789,7 +839,7 @@ k_stage_tiled(StageArgs<T> a)
             }
             T4 out;
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
-            a.Uout[c] = out;
+            stx(a.Uout, c, out);
             if (flags) atomicOr(a.health, flags);
             cfl.scen = s;
             if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
@@ -1247,6 +1297,10 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
             return set_err(c, SWE_ERR_MESH, "too many cells");
         off[i + 1] = off[i] + ms[i].n_total;
     }
+    // the stage kernels address every per-cell array with 32-bit byte
+    // offsets; the largest is the half-edge set, 12 values per cell
+    if ((unsigned long long)off[nm] * 12ull * c->tsize >= (1ull << 32))
+        return set_err(c, SWE_ERR_UNSUPPORTED, "too many cells for one context (a per-cell array would exceed 4 GiB)");
     const swe_mesh *m = &ms[0];
     const int n_ghost = nm == 1 ? m->n_total - m->n_owned : 0;
     int n_send = 0;
@@ -1565,13 +1619,15 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     float best = 1e30f;
     int best_b = c->block, best_g = c->grid_persist;
     int rc = SWE_OK;
+    // only launch shapes of the configured kernel: they give bitwise the same
+    // results (the tiled kernel is tiling-independent), the two kernels do not
     const int cell0 = c->cfg.cell_kernel;
+    const bool tiled = c->cfg.scheme != SWE_WAF && !cell0;
+    const bool f64 = c->cfg.precision == SWE_F64;
     int best_cell = cell0;
-    for (int cellk = 0; cellk < (c->cfg.scheme == SWE_WAF ? 1 : 2); ++cellk)
     for (int B : {64, 128, 256, 512}) {
-        if (B == 512 && (cellk || c->cfg.scheme == SWE_WAF)) continue;  // tiled kernel only
+        if (B == 512 && (!tiled || f64)) continue;  // FP32 tiled kernel only
         for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
-            c->cfg.cell_kernel = c->cfg.scheme == SWE_WAF ? cell0 : cellk;
             c->block = B;
             c->grid_persist = persist ? ncu * (2048 / B) : 0;
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);

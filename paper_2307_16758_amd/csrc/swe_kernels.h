@@ -38,7 +38,9 @@ struct ScenParams {
     int series_off, series_n;  // hydrograph points in the series arrays
 };
 
-template <typename T> struct Half { T h, b, un, ut; };
+// Interface values of one half-edge: depth, bed, normal and tangential
+// velocity, and the free surface eta = h + b as reconstructed.
+template <typename T> struct Half { T h, b, un, ut, eta; };
 
 // Division in the working precision: FP32 through the hardware reciprocal
 // (1 ulp; denormals are flushed in this build), FP64 exact.
@@ -95,6 +97,7 @@ __device__ __forceinline__ Half<T> reconstruct(const T4 &Uc, const T4 &Uk, const
     Half<T> r;
     r.h = Uc.x;
     r.b = Uc.w;
+    r.eta = Uc.x + Uc.w;
     frame_vel(Uc, nx, ny, eps, r.un, r.ut);
     if (SCHEME != kMUSCL) return r;
     if (!(Uc.x > eps) || !(Uk.x > eps)) return r;
@@ -135,6 +138,7 @@ __device__ __forceinline__ Half<T> reconstruct(const T4 &Uc, const T4 &Uk, const
     if (out[0] < T(0)) return r;
     r.h = out[0];
     r.b = out[1] - out[0];
+    r.eta = out[1];
     r.un = out[2];
     r.ut = out[3];
     return r;
@@ -365,65 +369,12 @@ __device__ __forceinline__ T limit2(T sb, T sf)
 {
     if (LIM == kZeroSlope) return T(0);
     const T p = sb * sf;
-    if (LIM == kVanAlbada) return p > T(0) ? p * (sb + sf) * frcp(sb * sb + sf * sf) : T(0);
+    // a true quotient: with FP64 denormals sb^2 + sf^2 can be far below
+    // 1 / DBL_MAX, where a reciprocal overflows and 0 * inf would give NaN
+    if (LIM == kVanAlbada) return p > T(0) ? fdiv(p * (sb + sf), sb * sb + sf * sf) : T(0);
     const T ab = fabs(sb), af = fabs(sf);
     const T m = LIM == kSuperbee ? tmax(tmin(T(2) * ab, af), tmin(ab, T(2) * af)) : tmin(ab, af);
     return p > T(0) ? copysign(m, sf) : T(0);
-}
-
-// Interface values of cell C across the edge with outward normal n (Sec.
-// 6.2.3 on the rotated states): K across the edge, A and B the upwind cells.
-template <typename T, typename T4, bool MUSCL_, int LIM>
-__device__ __forceinline__ Half<T> recon2(const Prim<T> &C, const Prim<T> &K, bool hk,
-                                          const Prim<T> &A, bool ha, const Prim<T> &B, bool hb,
-                                          T nx, T ny, T dm, const T4 &dist, float phi, T eps)
-{
-    Half<T> r;
-    r.h = C.h;
-    r.b = C.b;
-    r.un = C.u * nx + C.v * ny;
-    r.ut = -C.u * ny + C.v * nx;
-    if (!MUSCL_) return r;
-    if (!hk || !(C.h > eps) || !(K.h > eps)) return r;
-    if ((ha && !(A.h > eps)) || (hb && !(B.h > eps)) || (!ha && !hb)) return r;
-    const T qc[4] = {C.h, C.h + C.b, r.un, r.ut};
-    const T qk[4] = {K.h, K.h + K.b, K.u * nx + K.v * ny, -K.u * ny + K.v * nx};
-    T qu[4];
-    if (ha && hb) {
-        qu[0] = T(0.5) * (A.h + B.h);
-        qu[1] = T(0.5) * ((A.h + A.b) + (B.h + B.b));
-        qu[2] = T(0.5) * ((A.u * nx + A.v * ny) + (B.u * nx + B.v * ny));
-        qu[3] = T(0.5) * ((-A.u * ny + A.v * nx) + (-B.u * ny + B.v * nx));
-    } else {
-        const Prim<T> &O = ha ? A : B;
-        qu[0] = O.h;
-        qu[1] = O.h + O.b;
-        qu[2] = O.u * nx + O.v * ny;
-        qu[3] = -O.u * ny + O.v * nx;
-    }
-    T out[4];
-    bool done = false;
-    if (LIM == kLearned) {
-        if (phi >= 0.0f && phi <= 1.0f) {
-            const T p = T(phi);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) out[i] = qc[i] + dm * (p * ((qk[i] - qu[i]) * dist.z));
-            done = out[0] >= T(0);
-        }
-    }
-    if (!done) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const T sb = (qc[i] - qu[i]) * dist.x, sf = (qk[i] - qc[i]) * dist.y;
-            out[i] = qc[i] + dm * limit2<T, (LIM == kLearned ? kMinmod : LIM)>(sb, sf);
-        }
-    }
-    if (out[0] < T(0)) return r;
-    r.h = out[0];
-    r.b = out[1] - out[0];
-    r.un = out[2];
-    r.ut = out[3];
-    return r;
 }
 
 // Interface values of cell C across an interior edge with outward normal n
@@ -439,6 +390,7 @@ __device__ __forceinline__ Half<T> recon3(const Prim<T> &C, const Prim<T> &K, co
     Half<T> r;
     r.h = C.h;
     r.b = C.b;
+    r.eta = C.h + C.b;
     r.un = C.u * nx + C.v * ny;
     r.ut = -C.u * ny + C.v * nx;
     if (!MUSCL_) return r;
@@ -474,6 +426,7 @@ __device__ __forceinline__ Half<T> recon3(const Prim<T> &C, const Prim<T> &K, co
     if (out[0] < T(0)) return r;
     r.h = out[0];
     r.b = out[1] - out[0];
+    r.eta = out[1];
     r.un = out[2];
     r.ut = out[3];
     return r;
@@ -519,6 +472,61 @@ __device__ __forceinline__ void hllc_prim(T g, T eps, T hL, T uL, T vL, T hR, T 
     F[0] = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
     F[1] = (SR * GL1 - SL * GR1 + SR * SL * (qR - qL)) * inv;
     F[2] = F[0] * (Ss >= T(0) ? vL : vR);
+}
+
+// HLLC of Sec. 6.2.1 (the estimates of hllc_prim) in pressure-deviation
+// form: the mass flux F0, the tangential flux F2 and, for the normal
+// momentum, the flux less either side's hydrostatic pressure,
+// DL = F1 - g hL^2 / 2 and DR = F1 - g hR^2 / 2.  The pressure difference
+// enters as g (hL - hR)(hL + hR) / 2, so a state at rest (zero velocities,
+// equal depths) gives exactly zero in any precision.
+template <typename T>
+__device__ __forceinline__ void hllc_dev(T g, T eps, T hL, T uL, T vL, T hR, T uR, T vR, T &F0,
+                                         T &DL, T &DR, T &F2)
+{
+    const bool wl = hL > eps, wr = hR > eps;
+    if (!wl && !wr) {
+        F0 = T(0); F2 = T(0);
+        DL = -(T(0.5) * g * hL * hL);
+        DR = -(T(0.5) * g * hR * hR);
+        return;
+    }
+    if (!wl) { uL = T(0); vL = T(0); }
+    if (!wr) { uR = T(0); vR = T(0); }
+    const T qL = wl ? hL * uL : T(0), qR = wr ? hR * uR : T(0);
+    const T aL = sqrt(g * hL), aR = sqrt(g * hR);
+    T SL, SR, Ss;
+    if (!wr) {
+        SL = uL - aL; SR = uL + T(2) * aL; Ss = SR;
+    } else if (!wl) {
+        SL = uR - T(2) * aR; SR = uR + aR; Ss = SL;
+    } else {
+        const T h0 = T(0.5) * (hL + hR) - T(0.25) * (uR - uL) * (hL + hR) * frcp(aR + aL);
+        T hs;
+        if (h0 <= tmin(hL, hR)) {
+            const T t = T(0.5) * (aR + aL) + T(0.25) * (uL - uR);
+            hs = t > T(0) ? t * t * frcp(g) : T(0);
+        } else {
+            const T gL = sqrt(g * (h0 + hL) * frcp(T(2) * h0 * hL));
+            const T gR = sqrt(g * (h0 + hR) * frcp(T(2) * h0 * hR));
+            hs = (hL * gL + hR * gR + uL - uR) * frcp(gL + gR);
+        }
+        const T pL = hs > hL ? sqrt((hs + hL) * hs * frcp(T(2) * hL * hL)) : T(1);
+        const T pR = hs > hR ? sqrt((hs + hR) * hs * frcp(T(2) * hR * hR)) : T(1);
+        SL = uL - aL * pL;
+        SR = uR + aR * pR;
+        Ss = (SL * hR * (uR - SR) - SR * hL * (uL - SL)) * frcp(hR * (uR - SR) - hL * (uL - SL));
+    }
+    const T dP = T(0.5) * g * (hL - hR) * (hL + hR);  // pL - pR
+    const T mL = qL * uL, mR = qR * uR;                // advective momentum fluxes
+    if (SL >= T(0)) { F0 = qL; DL = mL; DR = mL + dP; F2 = qL * vL; return; }
+    if (SR <= T(0)) { F0 = qR; DL = mR - dP; DR = mR; F2 = qR * vR; return; }
+    const T inv = frcp(SR - SL);
+    F0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
+    const T base = SR * mL - SL * mR + SR * SL * (qR - qL);
+    DL = (base + SL * dP) * inv;
+    DR = (base + SR * dP) * inv;
+    F2 = F0 * (Ss >= T(0) ? vL : vR);
 }
 
 // A cell's share of an edge (Sec. 6.1): the oriented flux sg * G plus the
