@@ -321,6 +321,18 @@ static double limit_beta(double beta, double sb, double sf)
     return 0.0;
 }
 
+/* The learned slope kept inside the second-order TVD region of the
+ * backward and forward slopes (Sweby's bound 0 <= slope / s <= 2 with
+ * s the smaller of the two): zero unless both have the same sign, else the
+ * sign of the forward slope and at most twice the smaller magnitude.  With
+ * phi = 1 this is the monotonized central limiter on the central slope. */
+static double tvd_clip(double s, double sb, double sf)
+{
+    if (!(sb * sf > 0.0)) return 0.0;
+    double lim = 2.0 * fmin(fabs(sb), fabs(sf));
+    return copysign(fmin(fabs(s), lim), sf);
+}
+
 static double limit_vanalbada(double sb, double sf)
 {
     if (sb * sf > 0.0) return sb * sf * (sb + sf) / (sb * sb + sf * sf);
@@ -556,7 +568,10 @@ static iface reconstruct(const or_mesh *M, const or_params *P, const double *h, 
         double phi = mlp_forward(&v, f, P->mlp_bf16, a1, a2, &z);
         if (phi >= 0.0 && phi <= 1.0) { /* NaN fails both tests */
             double dc = hypot(M->cx[k] - xu, M->cy[k] - yu);
-            for (int i = 0; i < 4; ++i) out[i] = qc[i] + dm * phi * ((qk[i] - qu[i]) / dc);
+            for (int i = 0; i < 4; ++i) {
+                double sb = (qc[i] - qu[i]) / du, sf = (qk[i] - qc[i]) / df;
+                out[i] = qc[i] + dm * tvd_clip(phi * ((qk[i] - qu[i]) / dc), sb, sf);
+            }
             learned_ok = out[0] >= 0.0;
         }
     }

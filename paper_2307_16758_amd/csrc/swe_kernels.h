@@ -83,6 +83,17 @@ __device__ __forceinline__ T limit(T sb, T sf)
     return T(0);
 }
 
+// The learned limiter's slope s (phi times the central slope) kept inside
+// the second-order TVD region of the backward and forward slopes sb, sf:
+// zero unless they share a sign, else the sign of sf and at most
+// 2 min(|sb|, |sf|) (Sweby's bound; phi = 1 gives the monotonized central
+// limiter).  All three may carry the same positive factor (d_mid).
+template <typename T> __device__ __forceinline__ T tvd_clip(T s, T sb, T sf)
+{
+    const T lim = T(2) * tmin(fabs(sb), fabs(sf));
+    return sb * sf > T(0) ? copysign(tmin(fabs(s), lim), sf) : T(0);
+}
+
 // Interface values of cell c across one of its edges, in c's outward-normal
 // frame (Sec. 6.2.3 on the rotated states T_n U): h, b- and the normal and
 // tangential velocities.  Uk is the cell across the edge, Ua / Ub the two
@@ -124,7 +135,10 @@ __device__ __forceinline__ Half<T> reconstruct(const T4 &Uc, const T4 &Uk, const
         if (phi >= 0.0f && phi <= 1.0f) {  // a NaN fails both tests
             const T p = T(phi);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) out[i] = qc[i] + dm * (p * ((qk[i] - qu[i]) * dist.z));
+            for (int i = 0; i < 4; ++i) {
+                const T sb = (qc[i] - qu[i]) * dist.x, sf = (qk[i] - qc[i]) * dist.y;
+                out[i] = qc[i] + dm * tvd_clip(p * ((qk[i] - qu[i]) * dist.z), sb, sf);
+            }
             done = out[0] >= T(0);
         }
     }
@@ -413,7 +427,9 @@ __device__ __forceinline__ Half<T> recon3(const Prim<T> &C, const Prim<T> &K, co
         if (phi >= 0.0f && phi <= 1.0f) {
             const T p = T(phi);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) out[i] = qc[i] + p * (ga * (qk[i] - qu[i]));
+            for (int i = 0; i < 4; ++i)
+                out[i] = qc[i] + tvd_clip(p * (ga * (qk[i] - qu[i])), al * (qc[i] - qu[i]),
+                                          be * (qk[i] - qc[i]));
             done = out[0] >= T(0);
         }
     }

@@ -207,8 +207,11 @@ def evaluate_ladder(sc, weights, t_end, log=print):
     del ref
     area = _areas(sc, pc)
     out = {}
+    w_mc = np.zeros_like(weights)
+    w_mc[-1] = 1e3            # phi = 1: the monotonized central limiter (TVD bound)
     for name, prep, scen, lim, w, lev in [
             ("learned", pc, sc, swe.LEARNED, weights, 0),
+            ("phi1_mc", pc, sc, swe.LEARNED, w_mc, 0),
             ("minmod", pc, sc, swe.MINMOD, None, 0),
             ("vanalbada", pc, sc, swe.VANALBADA, None, 0),
             ("minmod_2x", p1, s1, swe.MINMOD, None, 1)]:

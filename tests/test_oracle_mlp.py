@@ -92,8 +92,13 @@ def test_nan_network_falls_back_to_minmod():
 
 
 def test_limiter_inputs_consistent_with_reconstruction():
-    """phi = 1 reproduces the central-slope interface values that the
-    limiter-input dump reports (q + d_mid * s), on every eligible half-edge."""
+    """phi = 1 is the monotonized central limiter on the central slope s of
+    the limiter-input dump: q + d_mid * clip(s) with clip(s) = 0 where the
+    backward and forward slopes disagree in sign, else sign(sf) *
+    min(|s|, 2 min(|sb|, |sf|)).  The backward/forward information comes
+    from the oracle's minmod reconstruction m = minmod(sb, sf) (|m| is the
+    smaller slope, m = 0 at an extremum), so this checks the learned path
+    against two independent pieces of the oracle and the textbook MC form."""
     sc = _river()
     M, h, hu, hv = _flowing(sc)
     w = np.zeros(O.MLP_NPAR)
@@ -101,13 +106,18 @@ def test_limiter_inputs_consistent_with_reconstruction():
     p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED, mlp=w)
     inp, phi = O.limiter_inputs(M, p, h, hu, hv)
     rh, rb, run, rut, sec = M.interfaces(p, h, hu, hv)
+    pm = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.MINMOD)
+    mh, mb, mun, mut, _ = M.interfaces(pm, h, hu, hv)
     elig = inp[..., 23] == 1.0
     assert elig.sum() > 100
     assert np.all(phi[elig] == 1.0) and np.all(phi[~elig] == 0.5)
-    rec = inp[..., 14:18] + inp[..., 22:23] * inp[..., 18:22]
-    ok = elig & (rec[..., 0] >= 0)
-    np.testing.assert_allclose(rh[ok], rec[..., 0][ok], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(rb[ok] + rh[ok], rec[..., 1][ok], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(run[ok], rec[..., 2][ok], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(rut[ok], rec[..., 3][ok], rtol=1e-12, atol=1e-12)
+    q, s, d = inp[..., 14:18], inp[..., 18:22], inp[..., 22:23]
+    mm = (np.stack([mh, mh + mb, mun, mut], -1) - q) / d          # minmod slopes
+    clip = np.where(mm == 0.0, 0.0, np.sign(mm) * np.minimum(np.abs(s), 2.0 * np.abs(mm)))
+    rec = q + d * clip
+    ok = elig & (rec[..., 0] >= 0) & (mh >= 0)
+    assert (np.abs(clip) < np.abs(s))[ok].any()       # the bound is active somewhere
+    scale = np.abs(q).max(axis=(0, 1)) + 1.0
+    for i, got in enumerate((rh, rb + rh, run, rut)):
+        np.testing.assert_allclose(got[ok], rec[..., i][ok], rtol=0, atol=1e-12 * scale[i])
     assert np.all(np.abs(inp[..., :12][elig][:, 0::3]) <= 1.0)
