@@ -226,15 +226,17 @@ int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
  * cell (child k at parent node k, 3 the central one).  The coarse state is
  * set to the restriction (mean of the children) at t = 0, and dev_rec
  * [3*n_total(coarse)][32] receives per half-edge: features[14], cell values
- * (h, eta, u_n, u_t)[4], central slopes[4], d_mid, target[4] = mean of the two
- * children touching the edge, valid flag, and the minmod interface values
- * (h, eta, u_n, u_t)[4] of the same half-edge.  Children out of range give
- * SWE_ERR_ARG. */
+ * (h, eta, u_n, u_t)[4], central slopes[4], the target distance d = d_mid / 2,
+ * target[4] = mean of the two children touching the edge (their mean
+ * centroid lies halfway from the cell centroid to the edge midpoint), valid
+ * flag, and the minmod interface values (h, eta, u_n, u_t)[4] at the edge
+ * midpoint.  Children out of range give SWE_ERR_ARG. */
 int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_children, float *dev_rec);
 
 /* Trainer: FP32 master weights and Adam moments on one device.  The loss of
  * n records (indices dev_idx into dev_rec[n_rec][32]) is
- * (1/n) sum sum_v wv[v] (q_v + d_mid phi s_v - t_v)^2 over v = h, eta, u_n, u_t. */
+ * (1/n) sum sum_v wv[v] (q_v + d phi s_v - t_v)^2 over v = h, eta, u_n, u_t
+ * (d: the record's target distance). */
 typedef struct swe_trainer swe_trainer;
 int swe_trainer_create(int device, const float *init_params, swe_trainer **out);
 void swe_trainer_destroy(swe_trainer *tr);

@@ -92,6 +92,19 @@ template <typename T> struct PhiArgs {
     T g, eps;
 };
 
+// Every LDS buffer of k_limiter_phi belongs to one wave, so its lanes
+// exchange data through LDS without a block barrier: the wave's LDS
+// operations are processed in order, and the compiler keeps the accesses to
+// the same buffers in program order; this waits for the wave's own
+// outstanding LDS operations and stops the compiler from moving LDS access
+// across it.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
 {
@@ -143,7 +156,7 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
     }
     const float b1a = w->b1[col], b1b = w->b1[16 + col], b2a = w->b2[col], b2b = w->b2[16 + col];
     const float w3a = w->W3[col], w3b = w->W3[16 + col], b3 = w->b3;
-    __syncthreads();
+    wave_lds_sync();
     for (int rt = 0; rt < 12; ++rt) {
         // A: row = col, k = kq..kq+3 of this 16-row tile
         const s4v A = *(const s4v *)&X[wv][rt * 16 + col][kq];
@@ -156,7 +169,7 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
             H[wv][kq + j][col] = bf16_bits(fmaxf(d0[j] + b1a, 0.f));
             H[wv][kq + j][16 + col] = bf16_bits(fmaxf(d1[j] + b1b, 0.f));
         }
-        __syncthreads();
+        wave_lds_sync();
         const s4v A0 = *(const s4v *)&H[wv][col][kq];
         const s4v A1 = *(const s4v *)&H[wv][col][16 + kq];
         f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, B2[0][0], z4, 0, 0, 0);
@@ -179,7 +192,7 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
                 if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -216,7 +229,7 @@ template <typename T> struct PairArgs {
 };
 
 // One record per coarse half-edge: features[14], q[4] = (h, eta, u_n, u_t) of
-// the cell, s[4] central slopes, d_mid, target[4], valid.
+// the cell, s[4] central slopes, target distance d_mid / 2, target[4], valid.
 template <typename T>
 __global__ void k_pairs(PairArgs<T> a)
 {
@@ -272,7 +285,11 @@ __global__ void k_pairs(PairArgs<T> a)
         frame_vel(fb, nx, ny, eps, ub, vb);
         const bool wet = fa.x > eps && fb.x > eps;
         for (int i = 0; i < 4; ++i) { r[14 + i] = float(qc[i]); r[18 + i] = float(s[i]); }
-        r[22] = float(ge.w);
+        // the two children touching edge m have their mean centroid halfway
+        // between the coarse centroid and the edge midpoint (red refinement:
+        // (5A + 5B + 2C) / 12 against (A + B + C) / 3 and (A + B) / 2), so
+        // the target is the fine solution at distance d_mid / 2
+        r[22] = float(T(0.5) * ge.w);
         r[23] = float(T(0.5) * (fa.x + fb.x));
         r[24] = float(T(0.5) * ((fa.x + fa.w) + (fb.x + fb.w)));
         r[25] = float(T(0.5) * (ua + ub));

@@ -124,7 +124,7 @@ def test_pairs_records():
     assert ok.sum() > 1000 and np.all(elig[ok])
     np.testing.assert_allclose(R[..., 14:18][ok], inp[..., 14:18][ok], rtol=1e-4, atol=1e-5)
     np.testing.assert_allclose(R[..., 18:22][ok], inp[..., 18:22][ok], rtol=1e-3, atol=1e-5)
-    np.testing.assert_allclose(R[..., 22], inp[..., 22], rtol=1e-6)
+    np.testing.assert_allclose(R[..., 22], 0.5 * inp[..., 22], rtol=1e-6)   # target distance
     assert np.abs(R[..., :14][ok] - inp[..., :14][ok]).max() < 1e-3
     # target depth: mean of the two children touching the edge
     for m in range(3):

@@ -38,7 +38,9 @@ def test_learned_limiter_beats_minmod_on_held_out_interfaces():
     idx = torch.arange(Rh.shape[0], dtype=torch.int32, device="cuda")
     learned_loss, _ = tr.loss_grad(Rh.contiguous().view(-1), idx, LT.WV)
     H = Rh.cpu().numpy().astype(np.float64)
-    minmod_loss = float((((H[:, 28:32] - H[:, 23:27]) ** 2) * LT.WV).sum(1).mean())
+    # minmod at the target point: halfway along its slope to the edge midpoint
+    mm_at_target = 0.5 * (H[:, 14:18] + H[:, 28:32])
+    minmod_loss = float((((mm_at_target - H[:, 23:27]) ** 2) * LT.WV).sum(1).mean())
     print(f"held-out interface misfit: learned {learned_loss:.4e}  minmod {minmod_loss:.4e}")
     assert learned_loss < minmod_loss
     res = LT.evaluate(held, refine_scenario(held), params, t_end=30.0)

@@ -121,3 +121,20 @@ def test_limiter_inputs_consistent_with_reconstruction():
     for i, got in enumerate((rh, rb + rh, run, rut)):
         np.testing.assert_allclose(got[ok], rec[..., i][ok], rtol=0, atol=1e-12 * scale[i])
     assert np.all(np.abs(inp[..., :12][elig][:, 0::3]) <= 1.0)
+
+
+def test_training_target_lies_halfway_to_the_edge():
+    """The target of a coarse half-edge is the mean of the two red-refinement
+    children touching the edge; their mean centroid is exactly halfway from
+    the coarse centroid to the edge midpoint, the distance the training
+    records store (d_mid / 2)."""
+    from swe_inputs.mesh import grid_mesh, refine_red
+    m = grid_mesh(30.0, 20.0, 6, 4, seed=7)
+    f = refine_red(m)
+    cen = m.xy[m.tri].mean(1)
+    fcen = f.xy[f.tri].mean(1)
+    for e in range(3):
+        mid = 0.5 * (m.xy[m.tri[:, e]] + m.xy[m.tri[:, (e + 1) % 3]])
+        ch = 4 * np.arange(m.n_cells)
+        tgt = 0.5 * (fcen[ch + e] + fcen[ch + (e + 1) % 3])
+        np.testing.assert_allclose(tgt, cen + 0.5 * (mid - cen), rtol=0, atol=1e-12)
