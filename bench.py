@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_STAGE1 = 98
 BYTES_STAGE2 = 114
 BYTES_EULER_F64 = 132   # first-order HLLC, FP64, stored geometry
+BYTES_EULER_F32 = 102   # first-order WAF / HLLC, FP32, stored geometry
 
 
 MUSCL_RK2 = dict(precision=0, scheme=1, integrator=1, limiter=0)
@@ -127,6 +128,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cell-kernel", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--scheme", choices=("muscl", "waf", "hllc1"), default="muscl",
+                    help="waf / hllc1: first-order WAF or HLLC with explicit Euler (FP32) instead "
+                         "of MUSCL-HLLC-RK2")
     ap.add_argument("--limiter", choices=("minmod", "learned"), default="minmod",
                     help="learned: the per-edge network (untrained weights: its cost, not its "
                          "accuracy) ahead of every stage")
@@ -154,6 +158,8 @@ def main():
     from paper_2307_16758_amd.problem import prepare_scenario
 
     sc, kw, P, k = workload(args.workload)
+    if args.scheme != "muscl":
+        kw = dict(kw, scheme=2 if args.scheme == "waf" else 0, integrator=0)
     if args.limiter == "learned":
         kw = dict(kw, limiter=swe.LEARNED)
     s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel, **kw)
@@ -226,10 +232,12 @@ def main():
         if kw["precision"] == 1:
             per_launch_bytes *= 2
     else:
-        per_launch_bytes = (BYTES_EULER_F64 if kw["precision"] == 1 else BYTES_STAGE1) * n_owned
+        per_launch_bytes = (BYTES_EULER_F64 if kw["precision"] == 1 else BYTES_EULER_F32) * n_owned
     achieved = per_launch_bytes / avg_launch_s / 1e9
     out = {
-        "metric": "cell-updates/s (MUSCL-HLLC, FP32, 1 GPU)",
+        "metric": "cell-updates/s ({}, {}, 1 GPU)".format(
+            "MUSCL-HLLC" if rk2 else ("WAF" if kw["scheme"] == 2 else "HLLC"),
+            "FP32" if kw["precision"] == 0 else "FP64"),
         "value": n_owned * args.steps / wall,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -242,7 +250,7 @@ def main():
         "dtype": "f32" if kw["precision"] == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
-                               f"{'MUSCL-HLLC-RK2' if rk2 else 'HLLC-Euler'}"
+                               f"{'MUSCL-HLLC-RK2' if rk2 else ('WAF' if kw['scheme'] == 2 else 'HLLC') + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
                                + (f", part of {P} with {k} ghost layers + pack" if P > 1 else ""),
                    "cells": n_owned, "tuned_launch": tuned,

@@ -194,9 +194,15 @@ int swe_local_dt(swe_ctx *ctx, double *dt); /* CFL step of the current state (sy
 int swe_health(swe_ctx *ctx, int *bits);    /* SWE_HEALTH_* bits since the last set_state */
 
 /* Gather the owned cells listed in send_idx into dev_sendbuf, laid out
- * [3][n_send] (h, hu, hv; context precision), in CSR order of the peers. */
+ * [3][n_send] (h, hu, hv; context precision), in CSR order of the peers.
+ * Asynchronous on the context stream, after the steps queued before it: the
+ * buffer is complete once that stream passes this point (swe_sync, or work
+ * queued after it on the same stream, e.g. the exchange). */
 int swe_pack_ghosts(swe_ctx *ctx, void *dev_sendbuf);
-/* Copy dev_recvbuf, laid out [3][n_total - n_owned], into the ghost cells. */
+/* Copy dev_recvbuf, laid out [3][n_total - n_owned], into the ghost cells.
+ * Asynchronous on the context stream: writes to dev_recvbuf issued on other
+ * streams must be complete before this call, and the buffer must stay
+ * unchanged until the stream passes it. */
 int swe_unpack_ghosts(swe_ctx *ctx, const void *dev_recvbuf);
 int swe_ghost_sizes(const swe_ctx *ctx, int32_t *n_send, int32_t *n_ghost);
 

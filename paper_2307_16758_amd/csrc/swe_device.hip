@@ -1740,7 +1740,6 @@ int swe_pack_ghosts(swe_ctx *c, void *buf)
         hipLaunchKernelGGL(k_pack_ghosts<float>, dim3(G), dim3(B), 0, c->stream, c->n_send,
                            c->send_idx, (const float4 *)Ucur, (float *)buf);
     HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipStreamSynchronize(c->stream));
     return SWE_OK;
 }
 
@@ -1759,7 +1758,6 @@ int swe_unpack_ghosts(swe_ctx *c, const void *buf)
         hipLaunchKernelGGL(k_unpack_ghosts<float>, dim3(G), dim3(B), 0, c->stream, c->n_owned,
                            c->n_ghost, (const float *)buf, (float4 *)Ucur);
     HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipStreamSynchronize(c->stream));
     return SWE_OK;
 }
 

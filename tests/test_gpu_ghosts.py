@@ -72,12 +72,15 @@ def test_pack_and_unpack():
     n_send, n_ghost = s.ghost_sizes()
     assert n_send == pr.sub.send_idx.size and n_ghost == pr.sub.n_total - pr.sub.n_owned
     buf = torch.empty(3 * n_send, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
     s.pack_ghosts(buf)
+    s.sync()                          # the pack runs on the library's stream
     st = s.read_state()
     b = buf.cpu().numpy().reshape(3, n_send)
     for f in range(3):
         assert np.array_equal(b[f], st[f][pr.sub.send_idx])
     rec = torch.arange(3 * n_ghost, dtype=torch.float32, device="cuda") * 1e-3 + 0.5
+    torch.cuda.synchronize()          # torch's writes before the library reads
     s.unpack_ghosts(rec)
     st2 = s.read_state()
     r = rec.cpu().numpy().reshape(3, n_ghost)
@@ -110,7 +113,9 @@ def test_exchange_reproduces_global(name, r):
         packed = []
         for s, pr in zip(subs, preps):
             buf = torch.empty(3 * max(1, pr.sub.send_idx.size), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
             s.pack_ghosts(buf)
+            s.sync()
             packed.append(buf[:3 * pr.sub.send_idx.size].view(3, -1))
         for q, (s, pr) in enumerate(zip(subs, preps)):
             n_ghost = pr.sub.n_total - pr.sub.n_owned
@@ -120,7 +125,10 @@ def test_exchange_reproduces_global(name, r):
                 js = list(ps.peers).index(q)
                 rb[:, pr.sub.recv_off[j]:pr.sub.recv_off[j + 1]] = \
                     packed[src][:, ps.send_off[js]:ps.send_off[js + 1]]
-            s.unpack_ghosts(rb[:, :n_ghost].contiguous().view(-1))
+            rv = rb[:, :n_ghost].contiguous().view(-1)
+            torch.cuda.synchronize()
+            s.unpack_ghosts(rv)
+            s.sync()
     for s, pr in zip(subs, preps):
         st = s.read_state()
         own = pr.sub.l2g[:pr.sub.n_owned]
