@@ -23,8 +23,10 @@
  *    returns from any call that reads or writes caller memory).
  *  - All buffers the library allocates are owned by the context and released
  *    by swe_destroy().
- *  - Work is issued on the context's stream (a stream the library creates,
- *    default priority, non-blocking).  swe_step() is asynchronous; health
+ *  - Work is issued on the context's stream (one the library creates,
+ *    default priority, non-blocking, or the caller's, swe_config.stream:
+ *    then the caller's own work on that stream is ordered with the
+ *    library's without synchronisation).  swe_step() is asynchronous; health
  *    errors (non-finite values, negative depths) are reported at the next
  *    synchronising call (swe_sync, swe_time, swe_read_state, swe_health).
  *  - One context per host thread; calls on one context are not thread-safe.
@@ -107,7 +109,10 @@ typedef struct {
                           the one-thread-per-cell kernel and FP64 use at most 256 */
     int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the
                           tiled kernel for HLLC1 and MUSCL (WAF always uses the cell kernel) */
-    int reserved[6];
+    void *stream;      /* NULL: the context creates its own stream (default priority,
+                          non-blocking); else a hipStream_t on `device`, borrowed: all of
+                          the context's work goes to it and it is never destroyed */
+    int reserved[4];
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).

@@ -13,6 +13,7 @@ struct swe_ctx {
     swe_config cfg{};
     int dev = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = true;  // false: borrowed from the caller (swe_config.stream)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::string err;
     bool has_mesh = false, has_state = false, ran = false;

@@ -648,8 +648,10 @@ k_stage_tiled(StageArgs<T> a)
         if (active) nb4 = ldx(a.nbr, c);
         dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur, active ? (int)((unsigned)nb4.w >> kScenShift) : -1,
                           a.dt_fixed);
+        T4 Ukeep;  // the cell's state, kept for phase 3
         if (active) {
             const T4 Uc = ldx(a.Uin, c);
+            Ukeep = Uc;
             const int nb[3] = {nb4.x, nb4.y, nb4.z};
             const unsigned word = (unsigned)nb4.w;
             sW[cl] = word;
@@ -789,15 +791,9 @@ k_stage_tiled(StageArgs<T> a)
         }
         __syncthreads();
         // ---- 3: cell sums, update, friction, cleanup, CFL
-        // the cell's state is read again (a cache hit) rather than held in
-        // registers across phase 2
         CflVal<T> cfl = cfl_none<T>();
-        T4 Uc;
-        unsigned word = 0u;
-        if (active) {
-            Uc = ldx(a.Uin, c);
-            word = sW[cl];
-        }
+        const T4 Uc = Ukeep;
+        const unsigned word = active ? sW[cl] : 0u;
         const int s = active ? (int)(word >> kScenShift) : -1;
         const double dtd = dt_finish(dtp, a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl,
                                      a.dt_max, a.dt_fixed);
@@ -1248,8 +1244,10 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     c->dev = cfg->device;
     c->tsize = cfg->precision == SWE_F64 ? 8 : 4;
     c->block = cfg->block ? cfg->block : 256;
+    c->own_stream = cfg->stream == nullptr;
+    if (!c->own_stream) c->stream = (hipStream_t)cfg->stream;
     if (hipSetDevice(c->dev) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        (c->own_stream && hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipMalloc(&c->health, sizeof(int)) != hipSuccess ||
         hipMalloc(&c->flag, sizeof(int)) != hipSuccess) {
@@ -1272,7 +1270,7 @@ void swe_destroy(swe_ctx *c)
     dfree_t(c->flag);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->stream && c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 

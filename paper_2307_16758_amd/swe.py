@@ -62,7 +62,8 @@ class swe_config(C.Structure):
                 ("integrator", C.c_int), ("limiter", C.c_int), ("waf_limiter", C.c_int),
                 ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
-                ("block", C.c_int), ("cell_kernel", C.c_int), ("reserved", C.c_int * 6)]
+                ("block", C.c_int), ("cell_kernel", C.c_int), ("stream", C.c_void_p),
+                ("reserved", C.c_int * 4)]
 
 
 class swe_mesh(C.Structure):
@@ -317,7 +318,12 @@ def _ptr(a, where):
 class Solver:
     """One swe_ctx: a sub-domain (or a whole mesh) on one GPU."""
 
-    def __init__(self, **cfg_kw):
+    def __init__(self, stream=None, **cfg_kw):
+        """stream: a torch.cuda.Stream (or raw hipStream_t handle) to borrow, so
+        that torch work on it and the library's work are ordered."""
+        if stream is not None:
+            cfg_kw["stream"] = getattr(stream, "cuda_stream", stream)
+        self._stream = stream             # keeps a borrowed torch stream alive
         self.cfg = config(**cfg_kw)
         self.dtype = np.float64 if self.cfg.precision == F64 else np.float32
         h = C.c_void_p()

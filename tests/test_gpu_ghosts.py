@@ -134,3 +134,33 @@ def test_exchange_reproduces_global(name, r):
         own = pr.sub.l2g[:pr.sub.n_owned]
         for f in range(3):
             assert np.array_equal(st[f][:pr.sub.n_owned], ref[f][own]), (name, f)
+
+
+def test_borrowed_stream_orders_with_torch():
+    """With the caller's stream borrowed (swe_config.stream), torch work
+    queued on that stream after a pack sees the packed buffer without any
+    synchronisation, and an unpack sees torch's writes made before it."""
+    import torch
+    swe, prepare_scenario = lib()
+    sc = wavy_scenario()
+    pr = prepare_scenario(sc, P=3, p=1, k=2)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=0, prepared=pr, stream=st)
+        s.step(4)
+        n_send, n_ghost = s.ghost_sizes()
+        buf = torch.zeros(3 * n_send, dtype=torch.float32, device="cuda")
+        s.pack_ghosts(buf)
+        packed = buf.clone()                       # queued on st, after the pack
+        rec = torch.arange(3 * n_ghost, dtype=torch.float32, device="cuda") * 1e-3 + 0.25
+        s.unpack_ghosts(rec)
+    state = s.read_state()
+    b = packed.cpu().numpy().reshape(3, n_send)
+    r = rec.cpu().numpy().reshape(3, n_ghost)
+    for f in range(3):
+        assert np.array_equal(state[f][pr.sub.n_owned:], r[f])
+    s2, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=0, prepared=pr)
+    s2.step(4)
+    ref = s2.read_state()
+    for f in range(3):
+        assert np.array_equal(b[f], ref[f][pr.sub.send_idx])
