@@ -152,8 +152,10 @@ const char *swe_strerror(int code);
  * neighbours, ghost and send ranges in bounds), geometry (areas, normals,
  * lengths, inscribed radii, MUSCL distances) and the device layout.
  * Replaces any previous mesh; the state must be set again afterwards.
- * SWE_ERR_UNSUPPORTED when a per-cell array would exceed 4 GiB (more than
- * about 89 million cells in FP32, 44 million in FP64, per context). */
+ * SWE_ERR_MESH for a mesh without cells; SWE_ERR_UNSUPPORTED when a
+ * per-cell array would exceed 4 GiB (more than about 89 million cells in
+ * FP32, 44 million in FP64, per context).  Both size checks come before any
+ * of the mesh's arrays is read. */
 int swe_mesh_upload(swe_ctx *ctx, const swe_mesh *mesh);
 
 /* Inflow hydrograph Q(t), piecewise linear through n points (clamped at the
@@ -172,7 +174,8 @@ int swe_read_state(swe_ctx *ctx, void *h, void *hu, void *hv, int where);
  * same kernel launches (one graph), each scenario with its own CFL step,
  * time, inflow and outflow.  State arrays of set_state / read_state are the
  * concatenation in the order given; swe_batch_offsets gives the first cell
- * of each scenario ([n_scen + 1] entries, may be NULL to get n_scen only). */
+ * of each scenario ([n_scen + 1] entries, may be NULL to get n_scen only).
+ * 1 <= n_meshes <= 32768, else SWE_ERR_ARG. */
 int swe_mesh_upload_batch(swe_ctx *ctx, int n_meshes, const swe_mesh *meshes);
 int swe_set_bc_series_scenario(swe_ctx *ctx, int scenario, int n, const double *t,
                                const double *q);

@@ -221,10 +221,11 @@ class Mesh:
                                    _i(self.nbr), _d(self.b), _d(self.manning))
         if not self.h:
             raise ValueError("oracle rejected the mesh (orientation or neighbour table)")
+        self._free = lib().or_mesh_free      # still reachable at interpreter exit
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_mesh_free(self.h)
+        if getattr(self, "h", None) and getattr(self, "_free", None):
+            self._free(self.h)
             self.h = None
 
     def geometry(self):

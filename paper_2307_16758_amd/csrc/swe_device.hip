@@ -1285,12 +1285,11 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     if (!c || !ms || nm <= 0 || nm > kMaxScenarios) return set_err(c, SWE_ERR_ARG, "bad argument");
     HIP_OK(c, hipSetDevice(c->dev));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    std::vector<HostGeometry> gs(nm);
+    // sizes first, before any array is read
     std::vector<int> off(nm + 1, 0);
     for (int i = 0; i < nm; ++i) {
-        std::string msg;
-        int rc = prepare_geometry(ms[i], i, gs[i], msg);
-        if (rc != SWE_OK) return set_err(c, rc, nm > 1 ? "mesh " + std::to_string(i) + ": " + msg : msg);
+        if (ms[i].n_total <= 0)
+            return set_err(c, SWE_ERR_MESH, nm > 1 ? "mesh " + std::to_string(i) + ": no cells" : "mesh: no cells");
         if ((long long)off[i] + ms[i].n_total > 0x7fffffffLL / 3)
             return set_err(c, SWE_ERR_MESH, "too many cells");
         off[i + 1] = off[i] + ms[i].n_total;
@@ -1299,6 +1298,12 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     // offsets; the largest is the half-edge set, 12 values per cell
     if ((unsigned long long)off[nm] * 12ull * c->tsize >= (1ull << 32))
         return set_err(c, SWE_ERR_UNSUPPORTED, "too many cells for one context (a per-cell array would exceed 4 GiB)");
+    std::vector<HostGeometry> gs(nm);
+    for (int i = 0; i < nm; ++i) {
+        std::string msg;
+        int rc = prepare_geometry(ms[i], i, gs[i], msg);
+        if (rc != SWE_OK) return set_err(c, rc, nm > 1 ? "mesh " + std::to_string(i) + ": " + msg : msg);
+    }
     const swe_mesh *m = &ms[0];
     const int n_ghost = nm == 1 ? m->n_total - m->n_owned : 0;
     int n_send = 0;

@@ -73,3 +73,14 @@ def python_neighbors(tri):
             else:
                 owner[key] = (c, m)
     return nbr
+
+
+def one_cell_basin(h=1.0, u=0.4, v=-0.2, b=0.1, n=0.03):
+    """A single triangle with walls on its three edges (the smallest mesh the
+    method accepts): still water or a uniform current in a closed cell."""
+    xy = np.array([[0.0, 0.0], [2.0, 0.3], [0.7, 1.8]])
+    tri = np.array([[0, 1, 2]], np.int32)
+    mesh = TriMesh(xy=xy, tri=tri, edge_side=np.array([[SIDE_BOTTOM, SIDE_RIGHT, SIDE_LEFT]], np.int8),
+                   info=dict(kind="one_cell"))
+    return Scenario("one_cell", mesh, np.full((1, 3), -1, np.int8), np.array([b]), np.array([n]),
+                    np.array([h]), np.array([h * u]), np.array([h * v]))

@@ -171,6 +171,43 @@ def test_manning_uniform_stream():
     np.testing.assert_allclose(hv, h0 * v0 / f, rtol=1e-12)
 
 
+@pytest.mark.parametrize("name,kw", SCHEMES)
+def test_closed_cell_friction_decay(name, kw):
+    """One triangle with walls: the wall pressures sum to zero around the
+    closed cell, so depth stays put and only Manning friction acts.  For
+    d|u|/dt = -k |u|^2, k = g n^2 h^(-4/3), the point-implicit update gives
+    1/|u| = 1/|u0| + k t exactly, whatever the (CFL) steps, and keeps the
+    direction of the current."""
+    from helpers import one_cell_basin
+    h0, u0, v0, n = 1.3, 0.5, -0.25, 0.035
+    sc = one_cell_basin(h=h0, u=u0, v=v0, n=n)
+    M = O.Mesh(sc.mesh.xy, sc.mesh.tri, np.full((1, 3), -1, np.int32), sc.b, sc.manning)
+    p = O.scenario_params(sc, **kw)
+    h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 80)
+    assert fl == 0 and t > 1.0
+    k = 9.81 * n * n * h0 ** (-4.0 / 3.0)
+    speed = 1.0 / (1.0 / math.hypot(u0, v0) + k * t)
+    # RK2 averages two friction-only Euler stages: the same ODE to O(dt^2)
+    tol = 1e-12 if kw.get("integrator", O.EULER) == O.EULER else 3e-5
+    assert abs(h[0] - h0) <= 1e-14 * h0
+    assert math.isclose(math.hypot(hu[0], hv[0]) / h[0], speed, rel_tol=tol)
+    assert math.isclose(hu[0] * v0, hv[0] * u0, rel_tol=1e-12)
+
+
+def test_all_dry_domain():
+    """No wet cell: no CFL step exists; with dt_max the state stays exactly
+    dry and the clock advances by dt_max per step."""
+    sc = dam_break_channel(Lx=20.0, Ly=4.0, nx=10, ny=2, h_left=0.0, h_right=0.0)
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc)
+    with pytest.raises(RuntimeError):
+        M.run(p, sc.h, sc.hu, sc.hv, 1)
+    p.dt_max = 0.25
+    h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 8)
+    assert fl == 0 and t == 2.0
+    assert not h.any() and not hu.any() and not hv.any()
+
+
 MIRROR_CASES = [SCHEMES[0], SCHEMES[2],
                 # The superbee WAF is left out on purpose: its ratio r jumps
                 # between -inf and +inf where the local jump of q vanishes
