@@ -617,8 +617,12 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 #ifndef SWE_TILED_WAVES
 #define SWE_TILED_WAVES 6  // FP32: waves per SIMD the register budget is sized for
 #endif
+#ifndef SWE_TILED_WAVES_LEARNED
+#define SWE_TILED_WAVES_LEARNED 5  // the learned-limiter instance needs 96 registers
+#endif
 template <typename T, bool MUSCL_, int LIM, int TILE>
-__global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? SWE_TILED_WAVES : 2)))
+__global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 ? (LIM == kLearned ? SWE_TILED_WAVES_LEARNED : SWE_TILED_WAVES) : 2)))
 k_stage_tiled(StageArgs<T> a)
 {
     using T4 = typename V4<T>::type;

@@ -60,6 +60,22 @@ __host__ __device__ inline float bf16_float(uint16_t b)
     return f;
 }
 __device__ __forceinline__ float bf16_round(float f) { return bf16_float(bf16_bits(f)); }
+// the same rounding (to nearest, ties to even) by the hardware conversion
+__device__ __forceinline__ uint16_t bf16_bits_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf16_round_hw(float f) { return (float)(__bf16)f; }
+
+// Sum over each row of 16 lanes, left in every lane of the row, by DPP moves
+// (no LDS): quad swaps (lane ^ 1, lane ^ 2), then rotations of the row by 4
+// and 8.  Lane 0 of a row adds in the order ((p0 + p1) + (p2 + p3)) + ...,
+// the order of a butterfly over lane ^ 1, ^ 2, ^ 4, ^ 8.
+__device__ __forceinline__ float row16_sum(float p)
+{
+    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0xB1, 0xF, 0xF, false));
+    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x4E, 0xF, 0xF, false));
+    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x124, 0xF, 0xF, false));
+    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x128, 0xF, 0xF, false));
+    return p;
+}
 
 __device__ __forceinline__ int xcd_tile_m(int bid, int nb)
 {
@@ -134,7 +150,7 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
             const bool ok = limiter_features<T, T4>(Uc, Un[m], hn[m], Un[ma], hn[ma], Un[mb],
                                                     hn[mb], ge.x, ge.y, ge.w, di, a.g, a.eps, f);
 #pragma unroll
-            for (int i = 0; i < kMlpIn; ++i) X[wv][3 * lane + m][i] = bf16_bits(f[i]);
+            for (int i = 0; i < kMlpIn; ++i) X[wv][3 * lane + m][i] = bf16_bits_hw(f[i]);
             // column 14 is padding; column 15 (zero weights) flags an eligible half-edge
             X[wv][3 * lane + m][14] = 0;
             X[wv][3 * lane + m][15] = ok ? 0x3F80 : 0;
@@ -166,8 +182,8 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         // D: rows kq + j, column col (and 16 + col)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            H[wv][kq + j][col] = bf16_bits(fmaxf(d0[j] + b1a, 0.f));
-            H[wv][kq + j][16 + col] = bf16_bits(fmaxf(d1[j] + b1b, 0.f));
+            H[wv][kq + j][col] = bf16_bits_hw(fmaxf(d0[j] + b1a, 0.f));
+            H[wv][kq + j][16 + col] = bf16_bits_hw(fmaxf(d1[j] + b1b, 0.f));
         }
         wave_lds_sync();
         const s4v A0 = *(const s4v *)&H[wv][col][kq];
@@ -179,11 +195,8 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         float p[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            p[j] = bf16_round(fmaxf(e0[j] + b2a, 0.f)) * w3a + bf16_round(fmaxf(e1[j] + b2b, 0.f)) * w3b;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) p[j] += __shfl_xor(p[j], o);
+            p[j] = row16_sum(bf16_round_hw(fmaxf(e0[j] + b2a, 0.f)) * w3a +
+                             bf16_round_hw(fmaxf(e1[j] + b2b, 0.f)) * w3b);
         if (col == 0) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
