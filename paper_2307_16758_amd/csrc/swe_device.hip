@@ -40,6 +40,79 @@ __device__ __forceinline__ double bitsd(unsigned long long b)
     return __longlong_as_double((long long)b);
 }
 
+// Cross-lane moves by DPP (no LDS round trip).  CTRL is the DPP control:
+// 0xB1 / 0x4E swap lanes within a quad (lane ^ 1, lane ^ 2), 0x124 / 0x128
+// rotate a row of 16 lanes by 4 / 8, 0x142 / 0x143 broadcast lane 15 of a
+// row to the next row / lane 31 to rows 2 and 3.  Rows outside ROWS keep
+// `old`.  64-bit values move as two 32-bit halves.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp32(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF, typename V>
+__device__ __forceinline__ V dpp(V old, V v)
+{
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, dpp32<CTRL, ROWS>(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v)));
+    } else {
+        const int2 o = __builtin_bit_cast(int2, old), x = __builtin_bit_cast(int2, v);
+        int2 r;
+        r.x = dpp32<CTRL, ROWS>(o.x, x.x);
+        r.y = dpp32<CTRL, ROWS>(o.y, x.y);
+        return __builtin_bit_cast(V, r);
+    }
+}
+template <typename V>
+__device__ __forceinline__ V lane_value(V v, int lane)  // lane: the same in every lane
+{
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    } else {
+        const int2 x = __builtin_bit_cast(int2, v);
+        int2 r;
+        r.x = __builtin_amdgcn_readlane(x.x, lane);
+        r.y = __builtin_amdgcn_readlane(x.y, lane);
+        return __builtin_bit_cast(V, r);
+    }
+}
+template <typename V> __device__ __forceinline__ V vmin(V a, V b) { return a < b ? a : b; }
+template <> __device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+template <> __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+template <typename V> __device__ __forceinline__ V vmax(V a, V b) { return a > b ? a : b; }
+template <> __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+template <> __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+
+// Minimum and maximum over groups of g lanes (g = 1, 2, 4, 8 or 16) when
+// every group of a row of 16 lanes holds the same g values: afterwards every
+// lane holds the group's minimum and maximum.  (With g = 8 the rotation by 4
+// joins a group's half with the other group's opposite half: the same
+// values.)  Every lane of the wave takes part.  min and max are exact, so
+// the order of the steps does not change the result.
+template <typename V>
+__device__ __forceinline__ void group_minmax(V &mn, V &mx, int g)
+{
+    if (g > 1) { mn = vmin(mn, dpp<0xB1>(mn, mn)); mx = vmax(mx, dpp<0xB1>(mx, mx)); }
+    if (g > 2) { mn = vmin(mn, dpp<0x4E>(mn, mn)); mx = vmax(mx, dpp<0x4E>(mx, mx)); }
+    if (g > 4) { mn = vmin(mn, dpp<0x124>(mn, mn)); mx = vmax(mx, dpp<0x124>(mx, mx)); }
+    if (g > 8) { mn = vmin(mn, dpp<0x128>(mn, mn)); mx = vmax(mx, dpp<0x128>(mx, mx)); }
+}
+
+// Minimum and maximum over the 64 lanes of the wave, returned in every lane
+// (every lane takes part).
+template <typename V>
+__device__ __forceinline__ void wave_minmax(V &mn, V &mx)
+{
+    group_minmax(mn, mx, 16);
+    mn = vmin(mn, dpp<0x142, 0xA>(mn, mn));
+    mx = vmax(mx, dpp<0x142, 0xA>(mx, mx));
+    mn = vmin(mn, dpp<0x143, 0xC>(mn, mn));
+    mx = vmax(mx, dpp<0x143, 0xC>(mx, mx));
+    mn = lane_value(mn, 63);
+    mx = lane_value(mx, 63);
+}
+
 __device__ __forceinline__ int xcd_tile(int bid, int nb)
 {
     // blocks are dealt to the 8 XCDs round-robin; give XCD x one contiguous
@@ -81,16 +154,13 @@ __device__ __forceinline__ double wave_step_dt(const ClockWord *clk, int ncopy, 
     for (;;) {
         const unsigned long long pend = __ballot(!have);
         if (pend == 0ull) break;
-        const int S = __shfl(s, __builtin_ctzll(pend));
-        // every group of ncopy lanes loads all copies, so the butterfly
-        // within the group leaves the full reduction in every lane
+        const int S = lane_value(s, __builtin_ctzll(pend));
+        // every group of ncopy lanes loads all copies, so the reduction
+        // within the group leaves the full result in every lane
         const ClockWord *q =
             clk + clock_off(ncopy, S, slot) + (size_t)(1 + (lane & (ncopy - 1))) * kClockLine;
         double mn = bitsd(q[kCfqMin]), mx = bitsd(q[kCfqMax]);
-        for (int o = ncopy >> 1; o > 0; o >>= 1) {
-            mn = fmin(mn, __shfl_xor(mn, o));
-            mx = fmax(mx, __shfl_xor(mx, o));
-        }
+        group_minmax(mn, mx, ncopy);
         if (s == S) {
             dt = cfl_dt(mn, mx, cfl, dt_max, rule);
             have = true;
@@ -115,7 +185,7 @@ __device__ __forceinline__ DtPrefetch dt_prefetch(const ClockWord *clk, int ncop
 {
     DtPrefetch p;
     const unsigned long long act = __ballot(s_own >= 0);
-    p.S = act ? __shfl(s_own, __builtin_ctzll(act)) : 0;
+    p.S = act ? lane_value(s_own, __builtin_ctzll(act)) : 0;
     p.mn = 0.0;
     p.mx = 0.0;
     if (dt_fixed <= 0.0) {
@@ -134,10 +204,7 @@ __device__ __forceinline__ double dt_finish(DtPrefetch p, const ClockWord *clk, 
     if (dt_fixed > 0.0) return dt_fixed;
     if (__ballot(s >= 0 && s != p.S) != 0ull)
         return wave_step_dt(clk, ncopy, slot, s, rule, cfl, dt_max, dt_fixed);
-    for (int o = ncopy >> 1; o > 0; o >>= 1) {
-        p.mn = fmin(p.mn, __shfl_xor(p.mn, o));
-        p.mx = fmax(p.mx, __shfl_xor(p.mx, o));
-    }
+    group_minmax(p.mn, p.mx, ncopy);
     return s >= 0 ? cfl_dt(p.mn, p.mx, cfl, dt_max, rule) : 0.0;
 }
 
@@ -208,15 +275,9 @@ __device__ __forceinline__ void cfl_commit(ClockWord *clk, int ncopy, int slot, 
 {
     const size_t copy = (size_t)(1 + (blockIdx.x & (ncopy - 1))) * kClockLine;
     int smin = v.scen >= 0 ? v.scen : 0x7fffffff, smax = v.scen;
-    for (int o = 32; o > 0; o >>= 1) {
-        smin = min(smin, __shfl_xor(smin, o));
-        smax = max(smax, __shfl_xor(smax, o));
-    }
+    wave_minmax(smin, smax);
     if (smin == smax) {
-        for (int o = 32; o > 0; o >>= 1) {
-            v.mn = fmin(v.mn, __shfl_xor(v.mn, o));
-            v.mx = fmax(v.mx, __shfl_xor(v.mx, o));
-        }
+        wave_minmax(v.mn, v.mx);
         v.scen = smax;
     } else {
         if (v.scen >= 0 && v.mx > T(0)) cfl_atomic(clk + clock_off(ncopy, v.scen, slot) + copy, rule, v);
