@@ -59,6 +59,13 @@ def workload(name):
         return config3(), MUSCL_RK2, 32, 4
     if name == "config5":
         return ensemble_scenarios(), MUSCL_RK2, 1, 0
+    if name == "dambreak_1m":
+        # WAF's own workload: config 1's wet dam break (h 1 m / 0.5 m, flat,
+        # walls, dx = 0.5 m) widened to 1118 x 447 quads = 999,492 cells; the
+        # rivers' dry banks break WAF's positivity
+        from swe_inputs import dam_break_channel
+        return (dam_break_channel(Lx=559.0, Ly=223.5, nx=1118, ny=447, x_dam=279.5),
+                dict(precision=0, scheme=2, integrator=0, limiter=0), 1, 0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -257,9 +264,14 @@ def main():
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload),
-                     "kernel": ("k_stage" if args.cell_kernel or kw["scheme"] == 2 else "k_stage_tiled")
-                     if not tuned else "autotuned stage kernel",
+                     # counters were taken on the plain-limiter stage kernel only
+                     "traffic": measured_traffic(args.workload)
+                     if (args.limiter == "minmod" and kw["scheme"] == 1 and not args.cell_kernel
+                         and not tuned) else None,
+                     "kernel": ("autotuned stage kernel" if tuned else
+                                ("k_stage" if args.cell_kernel or kw["scheme"] == 2 else "k_stage_tiled")
+                                + (" + k_limiter_phi (per-launch time covers both)"
+                                   if args.limiter == "learned" else "")),
                      "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_launch": per_launch_bytes},
         "health_bits": health,
