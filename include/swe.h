@@ -112,7 +112,11 @@ typedef struct {
     void *stream;      /* NULL: the context creates its own stream (default priority,
                           non-blocking); else a hipStream_t on `device`, borrowed: all of
                           the context's work goes to it and it is never destroyed */
-    int reserved[4];
+    int waves;         /* FP32 tiled kernel with 256-cell tiles (first-order HLLC and MUSCL
+                          with a classic limiter): waves per SIMD it is built for, 6 or 7;
+                          0 (default): 7 when that lets the chip hold every tile of a mesh
+                          of up to two rounds at once, else 6.  Same results either way. */
+    int reserved[3];
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).
@@ -185,9 +189,11 @@ int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
 /* Autotuner: times n_steps CFL steps for each launch shape of the
  * configured stage kernel (64, 128, 256 or, FP32 tiled kernel only, 512
  * threads per block; one tile per block or a persistent grid of
- * 2048 / block blocks per compute unit) from the current state, keeps the
- * fastest and restores the state, clocks and time.  The choice never
- * changes results (the tiled kernel is bitwise independent of the tiling).
+ * 2048 / block blocks per compute unit; with 256-cell FP32 tiles, builds for
+ * 6 and 7 waves per SIMD) from the current state, keeps the fastest and
+ * restores the state, clocks and time.  The choice never changes results
+ * (the tiled kernel is bitwise independent of the tiling, and both builds
+ * perform the same operations).
  * Outputs may be NULL. */
 int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
 

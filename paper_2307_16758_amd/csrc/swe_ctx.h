@@ -39,6 +39,8 @@ struct swe_ctx {
     // launch shape: threads per block and blocks of a persistent launch (0:
     // one tile per block); picked by swe_autotune when tuned
     int grid_persist = 0;
+    int waves = 0;  // tiled FP32 kernel, 256-cell tiles: 0 automatic, 6 or 7
+    int ncu = 0;    // compute units of the device
     bool tuned = false;
     double computed_inflow_len = 0.0, given_inflow_len = 0.0;
     long long step_count = 0;  // steps since set_state (selects clock slots and buffers)

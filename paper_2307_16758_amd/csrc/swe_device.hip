@@ -681,9 +681,9 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 #ifndef SWE_TILED_WAVES_LEARNED
 #define SWE_TILED_WAVES_LEARNED 5  // the learned-limiter instance needs 96 registers
 #endif
-template <typename T, bool MUSCL_, int LIM, int TILE>
+template <typename T, bool MUSCL_, int LIM, int TILE, int OCC = SWE_TILED_WAVES>
 __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 ? (LIM == kLearned ? SWE_TILED_WAVES_LEARNED : SWE_TILED_WAVES) : 2)))
+    sizeof(T) == 4 ? (LIM == kLearned ? SWE_TILED_WAVES_LEARNED : OCC) : 2)))
 k_stage_tiled(StageArgs<T> a)
 {
     using T4 = typename V4<T>::type;
@@ -1133,28 +1133,48 @@ int push_scenarios(swe_ctx *c)
 
 template <typename T> using KernelFn = void (*)(StageArgs<T>);
 
-template <typename T, int TILE> KernelFn<T> pick_tiled(int scheme, int lim)
+template <typename T, int TILE, int OCC = SWE_TILED_WAVES> KernelFn<T> pick_tiled(int scheme, int lim)
 {
-    if (scheme == kHLLC1) return k_stage_tiled<T, false, kMinmod, TILE>;
+    if (scheme == kHLLC1) return k_stage_tiled<T, false, kMinmod, TILE, OCC>;
     switch (lim) {
-    case kSuperbee: return k_stage_tiled<T, true, kSuperbee, TILE>;
-    case kVanAlbada: return k_stage_tiled<T, true, kVanAlbada, TILE>;
+    case kSuperbee: return k_stage_tiled<T, true, kSuperbee, TILE, OCC>;
+    case kVanAlbada: return k_stage_tiled<T, true, kVanAlbada, TILE, OCC>;
     case kLearned: return k_stage_tiled<T, true, kLearned, TILE>;
-    case kZeroSlope: return k_stage_tiled<T, true, kZeroSlope, TILE>;
-    default: return k_stage_tiled<T, true, kMinmod, TILE>;
+    case kZeroSlope: return k_stage_tiled<T, true, kZeroSlope, TILE, OCC>;
+    default: return k_stage_tiled<T, true, kMinmod, TILE, OCC>;
     }
+}
+
+// Seven waves per SIMD instead of six for the FP32 tiled kernel with
+// 256-cell tiles: each tile takes longer (72 registers instead of 80), but
+// the chip holds 7 instead of 6 tiles per compute unit.  Worth it when that
+// saves a round of tiles in a launch of at most two rounds (a sub-domain of
+// about 400k cells: one round instead of two); on larger meshes the two
+// are even, on config-2-sized ones six is faster.
+template <typename T> bool seven_waves(const swe_ctx *c, int B)
+{
+    if (sizeof(T) != 4 || B != 256 || c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel ||
+        (c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED))
+        return false;
+    if (c->waves) return c->waves == 7;
+    const long long nt = (c->n_total + B - 1) / B, s6 = 6LL * c->ncu, s7 = 7LL * c->ncu;
+    if (s6 <= 0) return false;
+    const long long r6 = (nt + s6 - 1) / s6, r7 = (nt + s7 - 1) / s7;
+    return r7 < r6 && r6 <= 2;
 }
 
 template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm);
 
 // Stage kernel of a configuration: the tiled kernel for first-order HLLC and
 // MUSCL (tile = block size 64, 128 or 256), the cell kernel for WAF.
-template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int block, int cell)
+template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int block, int cell,
+                                              bool w7)
 {
     if (scheme != kWAF && !cell) {
         if (block == 64) return pick_tiled<T, 64>(scheme, lim);
         if (block == 128) return pick_tiled<T, 128>(scheme, lim);
         if (block == 512 && sizeof(T) == 4) return pick_tiled<T, 512>(scheme, lim);
+        if (w7 && sizeof(T) == 4) return pick_tiled<T, 256, 7>(scheme, lim);
         return pick_tiled<T, 256>(scheme, lim);
     }
     return pick_cell_kernel<T>(scheme, lim, wafm);
@@ -1212,7 +1232,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     const bool cell_kernel = c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel;
     const int B = cell_kernel || sizeof(T) == 8 ? std::min(c->block, 256) : c->block;
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B,
-                                   c->cfg.cell_kernel);
+                                   c->cfg.cell_kernel, seven_waves<T>(c, B));
     const int ntiles = (c->n_total + B - 1) / B;
     const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
     const dim3 blk(B);
@@ -1299,7 +1319,8 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
         !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
-        cfg->cell_kernel < 0 || cfg->cell_kernel > 1)
+        cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
+        (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7))
         return SWE_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_ERR_DEVICE;
@@ -1309,13 +1330,15 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     c->dev = cfg->device;
     c->tsize = cfg->precision == SWE_F64 ? 8 : 4;
     c->block = cfg->block ? cfg->block : 256;
+    c->waves = cfg->waves;
     c->own_stream = cfg->stream == nullptr;
     if (!c->own_stream) c->stream = (hipStream_t)cfg->stream;
     if (hipSetDevice(c->dev) != hipSuccess ||
         (c->own_stream && hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipMalloc(&c->health, sizeof(int)) != hipSuccess ||
-        hipMalloc(&c->flag, sizeof(int)) != hipSuccess) {
+        hipMalloc(&c->flag, sizeof(int)) != hipSuccess ||
+        hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->dev) != hipSuccess) {
         swe_destroy(c);
         return SWE_ERR_DEVICE;
     }
@@ -1685,7 +1708,7 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     const bool graphs = c->use_graphs;
     c->use_graphs = false;
     float best = 1e30f;
-    int best_b = c->block, best_g = c->grid_persist;
+    int best_b = c->block, best_g = c->grid_persist, best_w = c->waves;
     int rc = SWE_OK;
     // only launch shapes of the configured kernel: they give bitwise the same
     // results (the tiled kernel is tiling-independent), the two kernels do not
@@ -1693,10 +1716,15 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     const bool tiled = c->cfg.scheme != SWE_WAF && !cell0;
     const bool f64 = c->cfg.precision == SWE_F64;
     int best_cell = cell0;
-    for (int B : {64, 128, 256, 512}) {
+    const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
+    for (int B : {64, 128, 256, 512})
+    for (int W : {6, 7}) {
         if (B == 512 && (!tiled || f64)) continue;  // FP32 tiled kernel only
+        // a second register budget only for the FP32 tiled kernel with 256-cell tiles
+        if (W == 7 && (B != 256 || !tiled || f64 || learned)) continue;
         for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
             c->block = B;
+            c->waves = W;
             c->grid_persist = persist ? ncu * (2048 / B) : 0;
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
@@ -1709,12 +1737,14 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
             rc = swe_last_step_ms(c, &ms);
             if (rc == SWE_OK && ms < best) {
                 best = ms; best_b = B; best_g = c->grid_persist; best_cell = c->cfg.cell_kernel;
+                best_w = W;
             }
         }
     }
     c->use_graphs = graphs;
     c->block = best_b;
     c->grid_persist = best_g;
+    c->waves = best_w;
     c->cfg.cell_kernel = best_cell;
     (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);

@@ -63,7 +63,7 @@ class swe_config(C.Structure):
                 ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
                 ("block", C.c_int), ("cell_kernel", C.c_int), ("stream", C.c_void_p),
-                ("reserved", C.c_int * 4)]
+                ("waves", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class swe_mesh(C.Structure):

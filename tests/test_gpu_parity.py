@@ -151,6 +151,22 @@ def test_tiled_results_do_not_depend_on_tile_size(name):
         assert ref[3] == out[3]
 
 
+@pytest.mark.parametrize("name", ["hllc1", "muscl_minmod_rk2", "muscl_superbee_rk2"])
+def test_six_and_seven_wave_builds_agree_bitwise(name):
+    """The 256-cell FP32 tiled kernel built for 6 or for 7 waves per SIMD
+    (the automatic choice depends on the mesh size) performs the same
+    operations: the same state and clock."""
+    sc = small_river()
+    outs = []
+    for waves in (6, 7):
+        s, _, _, _ = make_pair(sc, name, precision=0, block=256, waves=waves)
+        s.step(60)
+        outs.append(s.read_state() + (s.time(),))
+    for x, y in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(x, y)
+    assert outs[0][3] == outs[1][3]
+
+
 def test_runs_are_deterministic():
     sc = small_river()
     outs = []
