@@ -6,9 +6,10 @@
 //  * Inference (k_limiter_phi): BF16 weights and activations on the matrix
 //    cores (v_mfma_f32_16x16x16bf16_1k), FP32 accumulation.  One thread per
 //    cell builds the features of its three half-edges into LDS; each wave
-//    then runs 12 row tiles of 16 half-edges through both hidden layers
-//    (6 MFMAs per tile); the output layer is a 32-term dot product reduced
-//    across the 16 lanes that share a tile row.
+//    then runs 12 tiles of 16 half-edges through both hidden layers (6 MFMAs
+//    per tile, computed transposed so that layer 1's accumulators feed
+//    layer 2 directly); the output layer is a 32-term dot product, 8 terms
+//    per lane, summed over the 4 lanes that hold one half-edge.
 //  * Training data (k_restrict, k_pairs): the fine-mesh state restricted to
 //    the coarse mesh (mean of the four red-refinement children) gives the
 //    stencils; the target of a half-edge is the mean of the two children of
@@ -64,19 +65,6 @@ __device__ __forceinline__ float bf16_round(float f) { return bf16_float(bf16_bi
 __device__ __forceinline__ uint16_t bf16_bits_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf16_round_hw(float f) { return (float)(__bf16)f; }
 
-// Sum over each row of 16 lanes, left in every lane of the row, by DPP moves
-// (no LDS): quad swaps (lane ^ 1, lane ^ 2), then rotations of the row by 4
-// and 8.  Lane 0 of a row adds in the order ((p0 + p1) + (p2 + p3)) + ...,
-// the order of a butterfly over lane ^ 1, ^ 2, ^ 4, ^ 8.
-__device__ __forceinline__ float row16_sum(float p)
-{
-    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0xB1, 0xF, 0xF, false));
-    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x4E, 0xF, 0xF, false));
-    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x124, 0xF, 0xF, false));
-    p += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, p), 0x128, 0xF, 0xF, false));
-    return p;
-}
-
 __device__ __forceinline__ int xcd_tile_m(int bid, int nb)
 {
     const int x = bid & 7, i = bid >> 3, base = nb >> 3, rem = nb & 7;
@@ -126,7 +114,6 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
 {
     using T4 = typename V4<T>::type;
     __shared__ uint16_t X[4][192][16];
-    __shared__ uint16_t H[4][16][32];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c0 = xcd_tile_m(blockIdx.x, gridDim.x) * 256 + wv * 64;
     const int c = c0 + lane;
@@ -160,52 +147,59 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         for (int m = 0; m < 3; ++m)
             for (int i = 0; i < 16; ++i) X[wv][3 * lane + m][i] = 0;
     }
-    // weight fragments: lane supplies B[k = kq..kq+3][n = col (+16)]
+    // Both layers run transposed, units x half-edges: the weights are the A
+    // operand (lane: unit col (+16), inputs kq..kq+3 (+16)) and the layer
+    // input the B operand (lane: half-edge col, inputs kq..kq+3), so the
+    // accumulator of layer 1 (lane: units kq..kq+3, half-edge col) is, after
+    // bias, ReLU and BF16 rounding, the B operand of layer 2 as it stands
     const int col = lane & 15, kq = (lane >> 4) * 4;
     const MlpDev *w = a.w;
-    s4v B1[2], B2[2][2];
+    s4v W1f[2], W2f[2][2];
+    float b1r[2][4], b2r[2][4], w3r[2][4];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-        B1[nt] = *(const s4v *)&w->W1[(nt * 16 + col) * 16 + kq];
+        W1f[nt] = *(const s4v *)&w->W1[(nt * 16 + col) * 16 + kq];
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) B2[kb][nt] = *(const s4v *)&w->W2[(nt * 16 + col) * 32 + kb * 16 + kq];
+        for (int kb = 0; kb < 2; ++kb) W2f[kb][nt] = *(const s4v *)&w->W2[(nt * 16 + col) * 32 + kb * 16 + kq];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // the units of this lane's accumulator rows
+            b1r[nt][j] = w->b1[nt * 16 + kq + j];
+            b2r[nt][j] = w->b2[nt * 16 + kq + j];
+            w3r[nt][j] = w->W3[nt * 16 + kq + j];
+        }
     }
-    const float b1a = w->b1[col], b1b = w->b1[16 + col], b2a = w->b2[col], b2b = w->b2[16 + col];
-    const float w3a = w->W3[col], w3b = w->W3[16 + col], b3 = w->b3;
+    const float b3 = w->b3;
     wave_lds_sync();
     for (int rt = 0; rt < 12; ++rt) {
-        // A: row = col, k = kq..kq+3 of this 16-row tile
-        const s4v A = *(const s4v *)&X[wv][rt * 16 + col][kq];
+        // B: features kq..kq+3 of half-edge rt * 16 + col
+        const s4v xb = *(const s4v *)&X[wv][rt * 16 + col][kq];
         const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-        const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B1[0], z4, 0, 0, 0);
-        const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B1[1], z4, 0, 0, 0);
-        // D: rows kq + j, column col (and 16 + col)
+        const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, z4, 0, 0, 0);
+        const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, z4, 0, 0, 0);
+        s4v h0, h1;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            H[wv][kq + j][col] = bf16_bits_hw(fmaxf(d0[j] + b1a, 0.f));
-            H[wv][kq + j][16 + col] = bf16_bits_hw(fmaxf(d1[j] + b1b, 0.f));
+            h0[j] = (short)bf16_bits_hw(fmaxf(d0[j] + b1r[0][j], 0.f));
+            h1[j] = (short)bf16_bits_hw(fmaxf(d1[j] + b1r[1][j], 0.f));
         }
-        wave_lds_sync();
-        const s4v A0 = *(const s4v *)&H[wv][col][kq];
-        const s4v A1 = *(const s4v *)&H[wv][col][16 + kq];
-        f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, B2[0][0], z4, 0, 0, 0);
-        e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1, B2[1][0], e0, 0, 0, 0);
-        f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, B2[0][1], z4, 0, 0, 0);
-        e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1, B2[1][1], e1, 0, 0, 0);
-        float p[4];
+        f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, z4, 0, 0, 0);
+        e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][0], h1, e0, 0, 0, 0);
+        f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, z4, 0, 0, 0);
+        e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][1], h1, e1, 0, 0, 0);
+        // output layer: 8 of the 32 units in this lane, the rest in the
+        // lanes 16 and 32 apart (same half-edge)
+        float p = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            p[j] = row16_sum(bf16_round_hw(fmaxf(e0[j] + b2a, 0.f)) * w3a +
-                             bf16_round_hw(fmaxf(e1[j] + b2b, 0.f)) * w3b);
-        if (col == 0) {
+        for (int j = 0; j < 4; ++j) p += bf16_round_hw(fmaxf(e0[j] + b2r[0][j], 0.f)) * w3r[0][j];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = rt * 16 + kq + j;
-                const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-(p[j] + b3))) : 0.5f;
-                if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
-            }
+        for (int j = 0; j < 4; ++j) p += bf16_round_hw(fmaxf(e1[j] + b2r[1][j], 0.f)) * w3r[1][j];
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        if (lane < 16) {
+            const int row = rt * 16 + col;
+            const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-(p + b3))) : 0.5f;
+            if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
         }
-        wave_lds_sync();
     }
 }
 
