@@ -90,6 +90,12 @@ __device__ __forceinline__ T limit(T sb, T sf)
 // limiter).  All three may carry the same positive factor (d_mid).
 template <typename T> __device__ __forceinline__ T tvd_clip(T s, T sb, T sf)
 {
+    if constexpr (sizeof(T) == 4) {
+        // by median selections: 2 minmod(sb, sf) is the bound, and s (the
+        // scaled central slope, of the sign of sb and sf when they agree)
+        // is clipped between it and zero
+        return __builtin_amdgcn_fmed3f(s, 2.0f * __builtin_amdgcn_fmed3f(sb, sf, 0.0f), 0.0f);
+    }
     const T lim = T(2) * tmin(fabs(sb), fabs(sf));
     return sb * sf > T(0) ? copysign(tmin(fabs(s), lim), sf) : T(0);
 }
@@ -382,6 +388,16 @@ template <typename T, int LIM>
 __device__ __forceinline__ T limit2(T sb, T sf)
 {
     if (LIM == kZeroSlope) return T(0);
+    if constexpr (sizeof(T) == 4 && (LIM == kMinmod || LIM == kSuperbee)) {
+        // the same values by median selections (exact): minmod(a, b) is the
+        // median of a, b and 0; superbee is the larger in magnitude of
+        // minmod(2 sb, sf) and minmod(sb, 2 sf).  (Slopes whose product
+        // underflows keep their minmod value here instead of counting as zero.)
+        if (LIM == kMinmod) return __builtin_amdgcn_fmed3f(sb, sf, 0.0f);
+        const float s1 = __builtin_amdgcn_fmed3f(2.0f * sb, sf, 0.0f);
+        const float s2 = __builtin_amdgcn_fmed3f(sb, 2.0f * sf, 0.0f);
+        return sf > 0.0f ? fmaxf(s1, s2) : fminf(s1, s2);
+    }
     const T p = sb * sf;
     // a true quotient: with FP64 denormals sb^2 + sf^2 can be far below
     // 1 / DBL_MAX, where a reciprocal overflows and 0 * inf would give NaN
