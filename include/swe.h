@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 1
+#define SWE_ABI_VERSION 2
 
 /* status codes */
 #define SWE_OK 0
@@ -116,7 +116,18 @@ typedef struct {
                           with a classic limiter): waves per SIMD it is built for, 6 or 7;
                           0 (default): 7 when that lets the chip hold every tile of a mesh
                           of up to two rounds at once, else 6.  Same results either way. */
-    int reserved[3];
+    int reserved0;
+    /* Optional allocator of the context's device buffers (both NULL: hipMalloc
+     * and hipFree), e.g. a framework's caching allocator.  alloc(bytes, user)
+     * returns memory on `device` usable by the context's stream, or NULL (the
+     * call then fails with SWE_ERR_OOM); free(ptr, user) takes back a pointer
+     * alloc returned, and is called only after the context's stream has
+     * finished with it.  Both are called from the thread calling the library
+     * (mesh upload, series and weight setting, autotune, destroy). */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *alloc_user;
+    int reserved[2];
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).

@@ -59,3 +59,22 @@ int launch_limiter_phi(swe_ctx *c, const void *U);
 // Clock slots of a freshly set state U[0] (time t, CFL minima); syncs.
 int init_clock(swe_ctx *c, double t);
 }  // namespace swe
+
+// Device memory of a context: the configured allocator, else hipMalloc.
+// Freed only once the context's stream has finished with it.
+inline hipError_t dalloc(swe_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    if (!c->cfg.alloc) return hipMalloc(p, bytes);
+    *p = c->cfg.alloc(bytes, c->cfg.alloc_user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+inline void dfree(swe_ctx *c, void *&p)
+{
+    if (p) {
+        if (c->cfg.free) c->cfg.free(p, c->cfg.alloc_user);
+        else (void)hipFree(p);
+    }
+    p = nullptr;
+}

@@ -1024,26 +1024,21 @@ int set_err(swe_ctx *c, int code, const std::string &m)
                            std::string(#expr) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
-void dfree(void *&p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-template <typename P> void dfree_t(P *&p)
+template <typename P> void dfree_t(swe_ctx *c, P *&p)
 {
     void *v = p;
-    dfree(v);
+    dfree(c, v);
     p = nullptr;
 }
 
 void release_mesh(swe_ctx *c)
 {
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
-    dfree(c->nbr); dfree(c->cell); dfree(c->he_geo); dfree(c->he_dist);
-    dfree(c->he_co); dfree(c->he_lam); dfree(c->he_gam);
-    dfree(c->U[0]); dfree(c->U[1]); dfree(c->U1); dfree(c->tmp3); dfree(c->bed);
-    dfree_t(c->phi); dfree_t(c->clock); dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
-    dfree_t(c->t0); dfree_t(c->send_idx);
+    dfree(c, c->nbr); dfree(c, c->cell); dfree(c, c->he_geo); dfree(c, c->he_dist);
+    dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam);
+    dfree(c, c->U[0]); dfree(c, c->U[1]); dfree(c, c->U1); dfree(c, c->tmp3); dfree(c, c->bed);
+    dfree_t(c, c->phi); dfree_t(c, c->clock); dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
+    dfree_t(c, c->t0); dfree_t(c, c->send_idx);
     c->has_mesh = c->has_state = false;
 }
 
@@ -1064,16 +1059,16 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
 {
     const size_t n = c->n_total;
     std::vector<T> tmp;
-    HIP_OK(c, hipMalloc(&c->nbr, 16 * n));
+    HIP_OK(c, dalloc(c, (void **)&c->nbr, 16 * n));
     HIP_OK(c, hipMemcpy(c->nbr, g.nbr4.data(), 16 * n, hipMemcpyHostToDevice));
     to_t(g.cell, tmp);
-    HIP_OK(c, hipMalloc(&c->cell, 4 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->cell, 4 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->cell, tmp.data(), 4 * sizeof(T) * n, hipMemcpyHostToDevice));
     to_t(g.he_geo, tmp);
-    HIP_OK(c, hipMalloc(&c->he_geo, 12 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->he_geo, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_geo, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
     to_t(g.he_dist, tmp);
-    HIP_OK(c, hipMalloc(&c->he_dist, 12 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->he_dist, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_dist, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
     // compact half-edge set of the tiled kernel, formed in double and
     // rounded once: unit normal, the two MUSCL slope weights (the limiters
@@ -1094,17 +1089,19 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
             lam[e] = T(ge[2] * g.cell[4 * cc]);
             gam[e] = T(ge[3] * gd[2]);
         }
-    HIP_OK(c, hipMalloc(&c->he_co, 12 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->he_co, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_co, co.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
-    HIP_OK(c, hipMalloc(&c->he_lam, 3 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->he_lam, 3 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_lam, lam.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
-    HIP_OK(c, hipMalloc(&c->he_gam, 3 * sizeof(T) * n));
+    HIP_OK(c, dalloc(c, (void **)&c->he_gam, 3 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_gam, gam.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
     return SWE_OK;
 }
 
 int push_scenarios(swe_ctx *c)
 {
+    // the buffers below are replaced: the stream must be done with them
+    HIP_OK(c, hipStreamSynchronize(c->stream));
     c->h_ser_t.clear();
     c->h_ser_q.clear();
     for (size_t i = 0; i < c->h_scen.size(); ++i) {
@@ -1115,13 +1112,13 @@ int push_scenarios(swe_ctx *c)
             c->h_ser_q.insert(c->h_ser_q.end(), c->series[i].second.begin(), c->series[i].second.end());
         }
     }
-    dfree_t(c->scen); dfree_t(c->ser_t); dfree_t(c->ser_q);
-    HIP_OK(c, hipMalloc(&c->scen, sizeof(ScenParams) * c->h_scen.size()));
+    dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
+    HIP_OK(c, dalloc(c, (void **)&c->scen, sizeof(ScenParams) * c->h_scen.size()));
     HIP_OK(c, hipMemcpy(c->scen, c->h_scen.data(), sizeof(ScenParams) * c->h_scen.size(),
                         hipMemcpyHostToDevice));
     const size_t ns = std::max<size_t>(1, c->h_ser_t.size());
-    HIP_OK(c, hipMalloc(&c->ser_t, sizeof(double) * ns));
-    HIP_OK(c, hipMalloc(&c->ser_q, sizeof(double) * ns));
+    HIP_OK(c, dalloc(c, (void **)&c->ser_t, sizeof(double) * ns));
+    HIP_OK(c, dalloc(c, (void **)&c->ser_q, sizeof(double) * ns));
     if (!c->h_ser_t.empty()) {
         HIP_OK(c, hipMemcpy(c->ser_t, c->h_ser_t.data(), sizeof(double) * c->h_ser_t.size(),
                             hipMemcpyHostToDevice));
@@ -1320,7 +1317,7 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
         !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
-        (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7))
+        (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7) || (!cfg->alloc != !cfg->free))
         return SWE_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_ERR_DEVICE;
@@ -1336,8 +1333,8 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (hipSetDevice(c->dev) != hipSuccess ||
         (c->own_stream && hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipMalloc(&c->health, sizeof(int)) != hipSuccess ||
-        hipMalloc(&c->flag, sizeof(int)) != hipSuccess ||
+        dalloc(c, (void **)&c->health, sizeof(int)) != hipSuccess ||
+        dalloc(c, (void **)&c->flag, sizeof(int)) != hipSuccess ||
         hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->dev) != hipSuccess) {
         swe_destroy(c);
         return SWE_ERR_DEVICE;
@@ -1353,9 +1350,9 @@ void swe_destroy(swe_ctx *c)
     (void)hipSetDevice(c->dev);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release_mesh(c);
-    dfree(c->mlp);
-    dfree_t(c->health);
-    dfree_t(c->flag);
+    dfree(c, c->mlp);
+    dfree_t(c, c->health);
+    dfree_t(c, c->flag);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream && c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1447,17 +1444,17 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     int rc = c->cfg.precision == SWE_F64 ? upload_geometry<double>(c, g) : upload_geometry<float>(c, g);
     if (rc != SWE_OK) return rc;
     const size_t n = c->n_total, ts = c->tsize;
-    HIP_OK(c, hipMalloc(&c->U[0], 4 * ts * n));
-    HIP_OK(c, hipMalloc(&c->U[1], 4 * ts * n));
-    HIP_OK(c, hipMalloc(&c->U1, 4 * ts * n));
-    HIP_OK(c, hipMalloc(&c->tmp3, 3 * ts * n));
-    HIP_OK(c, hipMalloc(&c->bed, ts * n));
-    HIP_OK(c, hipMalloc(&c->phi, sizeof(float) * 3 * n));
+    HIP_OK(c, dalloc(c, (void **)&c->U[0], 4 * ts * n));
+    HIP_OK(c, dalloc(c, (void **)&c->U[1], 4 * ts * n));
+    HIP_OK(c, dalloc(c, (void **)&c->U1, 4 * ts * n));
+    HIP_OK(c, dalloc(c, (void **)&c->tmp3, 3 * ts * n));
+    HIP_OK(c, dalloc(c, (void **)&c->bed, ts * n));
+    HIP_OK(c, dalloc(c, (void **)&c->phi, sizeof(float) * 3 * n));
     // CFL partial copies: enough lines that concurrent block commits rarely
     // meet on one, few enough that large batches stay small
     c->ncopy = nm <= 64 ? 16 : (nm <= 1024 ? 8 : 4);
-    HIP_OK(c, hipMalloc(&c->clock, clock_bytes(c)));
-    HIP_OK(c, hipMalloc(&c->t0, sizeof(double) * (size_t)nm));
+    HIP_OK(c, dalloc(c, (void **)&c->clock, clock_bytes(c)));
+    HIP_OK(c, dalloc(c, (void **)&c->t0, sizeof(double) * (size_t)nm));
     {
         std::vector<double> bd(n);
         for (int i = 0; i < nm; ++i) std::copy(ms[i].cell_b, ms[i].cell_b + ms[i].n_total, bd.begin() + off[i]);
@@ -1469,7 +1466,7 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
         }
     }
     if (n_send > 0) {
-        HIP_OK(c, hipMalloc(&c->send_idx, sizeof(int) * n_send));
+        HIP_OK(c, dalloc(c, (void **)&c->send_idx, sizeof(int) * n_send));
         HIP_OK(c, hipMemcpy(c->send_idx, m->send_idx, sizeof(int) * n_send, hipMemcpyHostToDevice));
     }
     c->h_scen.assign(nm, ScenParams{});
@@ -1696,9 +1693,9 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     const size_t bytes = 4 * c->tsize * (size_t)c->n_total;
     void *saveU = nullptr;
     void *saveK = nullptr;
-    HIP_OK(c, hipMalloc(&saveU, bytes));
-    if (hipMalloc(&saveK, clock_bytes(c)) != hipSuccess) {
-        (void)hipFree(saveU);
+    HIP_OK(c, dalloc(c, &saveU, bytes));
+    if (dalloc(c, &saveK, clock_bytes(c)) != hipSuccess) {
+        dfree(c, saveU);
         return set_err(c, SWE_ERR_OOM, "autotune buffers");
     }
     const long long step0 = c->step_count;
@@ -1750,8 +1747,8 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);
     c->step_count = step0;
-    (void)hipFree(saveU);
-    (void)hipFree(saveK);
+    dfree(c, saveU);
+    dfree(c, saveK);
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
     if (rc != SWE_OK) return rc;
     c->tuned = true;

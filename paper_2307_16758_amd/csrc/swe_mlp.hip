@@ -505,7 +505,7 @@ int swe_limiter_set_weights(swe_ctx *c, const float *params)
     pack_mlp(params, w);
     if (hipSetDevice(c->dev) != hipSuccess) return err(c, SWE_ERR_DEVICE, "hipSetDevice");
     if (hipStreamSynchronize(c->stream) != hipSuccess) return err(c, SWE_ERR_DEVICE, "sync");
-    if (!c->mlp && hipMalloc(&c->mlp, sizeof(MlpDev)) != hipSuccess) return err(c, SWE_ERR_OOM, "alloc");
+    if (!c->mlp && dalloc(c, &c->mlp, sizeof(MlpDev)) != hipSuccess) return err(c, SWE_ERR_OOM, "alloc");
     if (hipMemcpy(c->mlp, &w, sizeof(MlpDev), hipMemcpyHostToDevice) != hipSuccess)
         return err(c, SWE_ERR_DEVICE, "copy");
     c->has_mlp = true;

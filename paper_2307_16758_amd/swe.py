@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # compiled with different flags for a measurement)
 LIB_PATH = os.environ.get("SWE_LIBRARY", os.path.join(HERE, "libswe.so"))
 
-SWE_ABI_VERSION = 1
+SWE_ABI_VERSION = 2
 SWE_OK = 0
 ERRORS = {-1: "SWE_ERR_ARG", -2: "SWE_ERR_MESH", -3: "SWE_ERR_STATE", -4: "SWE_ERR_NONFINITE",
           -5: "SWE_ERR_NEGATIVE_DEPTH", -6: "SWE_ERR_DEVICE", -7: "SWE_ERR_OOM",
@@ -57,13 +57,18 @@ i32p = C.POINTER(C.c_int32)
 f64p = C.POINTER(C.c_double)
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class swe_config(C.Structure):
     _fields_ = [("abi_version", C.c_int), ("precision", C.c_int), ("scheme", C.c_int),
                 ("integrator", C.c_int), ("limiter", C.c_int), ("waf_limiter", C.c_int),
                 ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
                 ("block", C.c_int), ("cell_kernel", C.c_int), ("stream", C.c_void_p),
-                ("waves", C.c_int), ("reserved", C.c_int * 3)]
+                ("waves", C.c_int), ("reserved0", C.c_int), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("reserved", C.c_int * 2)]
 
 
 class swe_mesh(C.Structure):
@@ -315,15 +320,42 @@ def _ptr(a, where):
     return C.c_void_p(a.ctypes.data)
 
 
+def torch_allocator(device=0, stream=None):
+    """(alloc, free) callbacks of the context configuration that take the
+    context's device buffers from PyTorch's caching allocator, associated
+    with ``stream`` (a torch.cuda.Stream; None: torch's current stream)."""
+    import torch
+
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except RuntimeError:
+            return None                   # the library reports SWE_ERR_OOM
+
+    def _free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
 class Solver:
     """One swe_ctx: a sub-domain (or a whole mesh) on one GPU."""
 
-    def __init__(self, stream=None, **cfg_kw):
+    def __init__(self, stream=None, allocator=None, **cfg_kw):
         """stream: a torch.cuda.Stream (or raw hipStream_t handle) to borrow, so
-        that torch work on it and the library's work are ordered."""
+        that torch work on it and the library's work are ordered.
+        allocator: None (hipMalloc) or "torch" (PyTorch's caching allocator
+        owns the context's device buffers)."""
         if stream is not None:
             cfg_kw["stream"] = getattr(stream, "cuda_stream", stream)
         self._stream = stream             # keeps a borrowed torch stream alive
+        self._alloc_cbs = None
+        if allocator == "torch":
+            torch_stream = stream if hasattr(stream, "cuda_stream") else None
+            self._alloc_cbs = torch_allocator(cfg_kw.get("device", 0), torch_stream)
+            cfg_kw["alloc"], cfg_kw["free"] = self._alloc_cbs
+        elif allocator is not None:
+            raise ValueError("allocator: None or 'torch'")
         self.cfg = config(**cfg_kw)
         self.dtype = np.float64 if self.cfg.precision == F64 else np.float32
         h = C.c_void_p()
@@ -333,8 +365,9 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None):
-            _lib.swe_destroy(self.ctx)
+            _lib.swe_destroy(self.ctx)    # frees through the callbacks, still alive here
             self.ctx = None
+        self._alloc_cbs = None
 
     def __del__(self):
         self.close()

@@ -119,3 +119,34 @@ def test_config3_full_largest_part_bit_exact():
         for f in ("l2g", "layer", "owner", "nbr", "peers", "recv_off", "send_off", "send_idx"):
             np.testing.assert_array_equal(getattr(b, f), getattr(a, f), err_msg=f)
     assert time.time() - t0 < 600
+
+
+def test_config_and_mesh_structs_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets of the
+    C structs that include/swe.h declares (compiled here with gcc)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2307_16758_amd import swe
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "swe.h")
+    fields = {"swe_config": [f[0] for f in swe.swe_config._fields_],
+              "swe_mesh": [f[0] for f in swe.swe_mesh._fields_]}
+    lines = [f'#include "{hdr}"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for st, names in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'printf("{st}.{n} %zu\\n", offsetof({st}, {n}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for st, names in fields.items():
+        cls = getattr(swe, st)
+        assert int(out[st]) == C.sizeof(cls), st
+        for n in names:
+            assert int(out[f"{st}.{n}"]) == getattr(cls, n).offset, (st, n)
