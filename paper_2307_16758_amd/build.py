@@ -28,6 +28,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-ffp-contract=on",
              "-Wno-unused-result"] + os.environ.get("SWE_EXTRA_HIPFLAGS", "").split()
 
+# per source: the network kernels keep MFMA accumulators in ordinary vector
+# registers (no moves out of accumulation registers between layers)
+FILE_FLAGS = {"swe_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 
 def run(cmd):
     print(" ".join(cmd), flush=True)
@@ -43,7 +47,7 @@ def build(verbose: bool = True, out: str = LIB, flags=None) -> str:
     objs = [obj]
     for src in ("swe_device.hip", "swe_mlp.hip"):
         o = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
-        run([HIPCC] + hip_flags + ["-c", os.path.join(CSRC, src), "-o", o])
+        run([HIPCC] + hip_flags + FILE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     tmp = out + f".tmp{os.getpid()}"
     run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)

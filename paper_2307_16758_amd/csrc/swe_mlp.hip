@@ -6,10 +6,9 @@
 //  * Inference (k_limiter_phi): BF16 weights and activations on the matrix
 //    cores (v_mfma_f32_16x16x16bf16_1k), FP32 accumulation.  One thread per
 //    cell builds the features of its three half-edges into LDS; each wave
-//    then runs 12 tiles of 16 half-edges through both hidden layers (6 MFMAs
-//    per tile, computed transposed so that layer 1's accumulators feed
-//    layer 2 directly); the output layer is a 32-term dot product, 8 terms
-//    per lane, summed over the 4 lanes that hold one half-edge.
+//    then runs 12 tiles of 16 half-edges through the network (8 MFMAs per
+//    tile, all layers computed transposed so that each accumulator feeds
+//    the next layer directly, biases as the accumulators' initial values).
 //  * Training data (k_restrict, k_pairs): the fine-mesh state restricted to
 //    the coarse mesh (mean of the four red-refinement children) gives the
 //    stencils; the target of a half-edge is the mean of the two children of
@@ -32,6 +31,8 @@ using namespace swe;
 
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -64,6 +65,15 @@ __device__ __forceinline__ float bf16_round(float f) { return bf16_float(bf16_bi
 // the same rounding (to nearest, ties to even) by the hardware conversion
 __device__ __forceinline__ uint16_t bf16_bits_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf16_round_hw(float f) { return (float)(__bf16)f; }
+// ReLU of an MFMA accumulator (4 values), rounded to BF16 and packed as the
+// B operand of the next MFMA (two values per conversion)
+__device__ __forceinline__ s4v relu_bf16x4(f4v d)
+{
+    const f2v lo = {fmaxf(d[0], 0.f), fmaxf(d[1], 0.f)}, hi = {fmaxf(d[2], 0.f), fmaxf(d[3], 0.f)};
+    const unsigned a = __builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf2v));
+    const unsigned b = __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf2v));
+    return __builtin_bit_cast(s4v, (unsigned long long)a | ((unsigned long long)b << 32));
+}
 
 __device__ __forceinline__ int xcd_tile_m(int bid, int nb)
 {
@@ -147,57 +157,48 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         for (int m = 0; m < 3; ++m)
             for (int i = 0; i < 16; ++i) X[wv][3 * lane + m][i] = 0;
     }
-    // Both layers run transposed, units x half-edges: the weights are the A
-    // operand (lane: unit col (+16), inputs kq..kq+3 (+16)) and the layer
-    // input the B operand (lane: half-edge col, inputs kq..kq+3), so the
-    // accumulator of layer 1 (lane: units kq..kq+3, half-edge col) is, after
-    // bias, ReLU and BF16 rounding, the B operand of layer 2 as it stands
+    // All three layers run transposed, units x half-edges: the weights are
+    // the A operand (lane: unit col (+16), inputs kq..kq+3 (+16)), the layer
+    // input the B operand (lane: half-edge col, inputs kq..kq+3) and the
+    // bias the accumulator's initial value (lane: units kq..kq+3), so a
+    // layer's accumulator (lane: units kq..kq+3 of half-edge col) is, after
+    // ReLU and BF16 rounding, the next layer's B operand as it stands.  The
+    // output layer has W3 in row 0 of A (the other rows zero): its result
+    // for half-edge col is row 0, i.e. element 0 in lanes 0..15.
     const int col = lane & 15, kq = (lane >> 4) * 4;
     const MlpDev *w = a.w;
-    s4v W1f[2], W2f[2][2];
-    float b1r[2][4], b2r[2][4], w3r[2][4];
+    s4v W1f[2], W2f[2][2], W3f[2];
+    f4v b1v[2], b2v[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
         W1f[nt] = *(const s4v *)&w->W1[(nt * 16 + col) * 16 + kq];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) W2f[kb][nt] = *(const s4v *)&w->W2[(nt * 16 + col) * 32 + kb * 16 + kq];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // the units of this lane's accumulator rows
-            b1r[nt][j] = w->b1[nt * 16 + kq + j];
-            b2r[nt][j] = w->b2[nt * 16 + kq + j];
-            w3r[nt][j] = w->W3[nt * 16 + kq + j];
+        for (int j = 0; j < 4; ++j) {
+            b1v[nt][j] = w->b1[nt * 16 + kq + j];
+            b2v[nt][j] = w->b2[nt * 16 + kq + j];
+            W3f[nt][j] = col == 0 ? (short)bf16_bits_hw(w->W3[nt * 16 + kq + j]) : (short)0;
         }
     }
-    const float b3 = w->b3;
+    const f4v c3 = {kq == 0 ? w->b3 : 0.f, 0.f, 0.f, 0.f};
     wave_lds_sync();
     for (int rt = 0; rt < 12; ++rt) {
         // B: features kq..kq+3 of half-edge rt * 16 + col
         const s4v xb = *(const s4v *)&X[wv][rt * 16 + col][kq];
-        const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-        const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, z4, 0, 0, 0);
-        const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, z4, 0, 0, 0);
-        s4v h0, h1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            h0[j] = (short)bf16_bits_hw(fmaxf(d0[j] + b1r[0][j], 0.f));
-            h1[j] = (short)bf16_bits_hw(fmaxf(d1[j] + b1r[1][j], 0.f));
-        }
-        f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, z4, 0, 0, 0);
+        const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, b1v[0], 0, 0, 0);
+        const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, b1v[1], 0, 0, 0);
+        const s4v h0 = relu_bf16x4(d0), h1 = relu_bf16x4(d1);
+        f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, b2v[0], 0, 0, 0);
         e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][0], h1, e0, 0, 0, 0);
-        f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, z4, 0, 0, 0);
+        f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, b2v[1], 0, 0, 0);
         e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][1], h1, e1, 0, 0, 0);
-        // output layer: 8 of the 32 units in this lane, the rest in the
-        // lanes 16 and 32 apart (same half-edge)
-        float p = 0.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) p += bf16_round_hw(fmaxf(e0[j] + b2r[0][j], 0.f)) * w3r[0][j];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) p += bf16_round_hw(fmaxf(e1[j] + b2r[1][j], 0.f)) * w3r[1][j];
-        p += __shfl_xor(p, 16);
-        p += __shfl_xor(p, 32);
+        const s4v g0 = relu_bf16x4(e0), g1 = relu_bf16x4(e1);
+        f4v o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W3f[0], g0, c3, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W3f[1], g1, o, 0, 0, 0);
         if (lane < 16) {
             const int row = rt * 16 + col;
-            const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-(p + b3))) : 0.5f;
+            const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-o[0])) : 0.5f;
             if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
         }
     }
