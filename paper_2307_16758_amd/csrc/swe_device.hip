@@ -486,20 +486,17 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
         const T g = a.g, eps = a.eps;
         const T4 Uc = a.Uin[c];
         const T4 cg = a.cell[c];
-        const int nbr[3] = {nb4.x, nb4.y, nb4.z};
-        T4 Un[3];
-        bool hn[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            hn[m] = nbr[m] >= 0;
-            Un[m] = hn[m] ? a.Uin[nbr[m]] : Uc;
-        }
+        // neighbours in separate variables, picked by selects: a local
+        // array indexed at run time would live in scratch memory
+        const int nb0 = nb4.x, nb1 = nb4.y, nb2 = nb4.z;
+        const bool hn0 = nb0 >= 0, hn1 = nb1 >= 0, hn2 = nb2 >= 0;
+        const T4 Un0 = hn0 ? a.Uin[nb0] : Uc, Un1 = hn1 ? a.Uin[nb1] : Uc, Un2 = hn2 ? a.Uin[nb2] : Uc;
         T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const T4 ge = a.he_geo[3 * c + m];
             const T nx = ge.x, ny = ge.y, L = ge.z;
-            const int k = nbr[m];
+            const int k = m == 0 ? nb0 : (m == 1 ? nb1 : nb2);
             if (k < 0) {
                 const ScenParams sp = a.scen[s];
                 const double t_st =
@@ -515,6 +512,11 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
                 continue;
             }
             const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+            const T4 Um = m == 0 ? Un0 : (m == 1 ? Un1 : Un2);
+            const T4 Ua = ma == 0 ? Un0 : (ma == 1 ? Un1 : Un2);
+            const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
+            const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
+            const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
             const int jb = (word >> (2 * m)) & 3;
             T4 zero4;
             zero4.x = T(0); zero4.y = T(0); zero4.z = T(0); zero4.w = T(0);
@@ -537,9 +539,9 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
                 dmk = a.he_geo[3 * k + jb].w;
                 if (LIM == kLearned) { phic = a.phi[3 * c + m]; phik = a.phi[3 * k + jb]; }
             }
-            const Half<T> own = reconstruct<T, T4, SCHEME, LIM>(Uc, Un[m], Un[ma], hn[ma], Un[mb],
-                                                                hn[mb], nx, ny, ge.w, dc, phic, eps);
-            const Half<T> oth = reconstruct<T, T4, SCHEME, LIM>(Un[m], Uc, Uka, hka, Ukb, hkb, -nx,
+            const Half<T> own = reconstruct<T, T4, SCHEME, LIM>(Uc, Um, Ua, ha, Ub, hb, nx, ny, ge.w,
+                                                                dc, phic, eps);
+            const Half<T> oth = reconstruct<T, T4, SCHEME, LIM>(Um, Uc, Uka, hka, Ukb, hkb, -nx,
                                                                 -ny, dmk, dk, phik, eps);
             // hydrostatic reconstruction
             const T be = tmax(own.b, oth.b);
@@ -560,14 +562,16 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
             T F[3];
             if (SCHEME == kWAF) {
                 const T4 dw = a.he_dist[3 * c + m];
-                const T4 &ULc = isL ? Uc : Un[m];
-                const T4 &URc = isL ? Un[m] : Uc;
+                // values, not references: a reference chosen at run time
+                // would put both states in scratch memory
+                const T4 ULc = isL ? Uc : Um;
+                const T4 URc = isL ? Um : Uc;
                 WafIn<T> w;
                 w.eL = ULc.x + ULc.w; w.eR = URc.x + URc.w;
                 w.vL = tangential(ULc, nLx, nLy, eps);
                 w.vR = tangential(URc, nLx, nLy, eps);
                 T eo, vo, ek, vk;
-                const bool ho = waf_upwind(Un[ma], hn[ma], Un[mb], hn[mb], nLx, nLy, eps, eo, vo);
+                const bool ho = waf_upwind(Ua, ha, Ub, hb, nLx, nLy, eps, eo, vo);
                 const bool hk = waf_upwind(Uka, hka, Ukb, hkb, nLx, nLy, eps, ek, vk);
                 if (isL) { w.eLu = eo; w.vLu = vo; w.hasLu = ho; w.eRu = ek; w.vRu = vk; w.hasRu = hk; }
                 else { w.eLu = ek; w.vLu = vk; w.hasLu = hk; w.eRu = eo; w.vRu = vo; w.hasRu = ho; }
