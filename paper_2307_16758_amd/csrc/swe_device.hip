@@ -490,7 +490,10 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
         // array indexed at run time would live in scratch memory
         const int nb0 = nb4.x, nb1 = nb4.y, nb2 = nb4.z;
         const bool hn0 = nb0 >= 0, hn1 = nb1 >= 0, hn2 = nb2 >= 0;
-        const T4 Un0 = hn0 ? a.Uin[nb0] : Uc, Un1 = hn1 ? a.Uin[nb1] : Uc, Un2 = hn2 ? a.Uin[nb2] : Uc;
+        // (the index is selected, not the value: a select between a load and
+        // a local value becomes a load through a selected pointer, which
+        // puts the local value in scratch memory)
+        const T4 Un0 = a.Uin[hn0 ? nb0 : c], Un1 = a.Uin[hn1 ? nb1 : c], Un2 = a.Uin[hn2 ? nb2 : c];
         T acc0 = T(0), acc1 = T(0), acc2 = T(0);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {

@@ -129,23 +129,28 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
     const int c = c0 + lane;
     if (c < a.n) {
         const int4 nb4 = a.nbr[c];
-        const int nb[3] = {nb4.x, nb4.y, nb4.z};
         const T4 Uc = a.U[c];
-        T4 Un[3];
-        bool hn[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            hn[m] = nb[m] >= 0;
-            Un[m] = hn[m] ? a.U[nb[m]] : Uc;
-        }
+        // neighbours in separate variables, picked by selects (a local array
+        // indexed at run time would live in scratch memory)
+        const bool hn0 = nb4.x >= 0, hn1 = nb4.y >= 0, hn2 = nb4.z >= 0;
+        // (the index is selected, not the value: a select between a load and
+        // a local value becomes a load through a selected pointer, which
+        // puts the local value in scratch memory)
+        const T4 Un0 = a.U[hn0 ? nb4.x : c], Un1 = a.U[hn1 ? nb4.y : c], Un2 = a.U[hn2 ? nb4.z : c];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const int ma = (m + 1) % 3, mb = (m + 2) % 3;
             const T4 ge = a.he_geo[3 * c + m];
             const T4 di = a.he_dist[3 * c + m];
+            const T4 Um = m == 0 ? Un0 : (m == 1 ? Un1 : Un2);
+            const T4 Ua = ma == 0 ? Un0 : (ma == 1 ? Un1 : Un2);
+            const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
+            const bool hm = m == 0 ? hn0 : (m == 1 ? hn1 : hn2);
+            const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
+            const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
             float f[kMlpIn];
-            const bool ok = limiter_features<T, T4>(Uc, Un[m], hn[m], Un[ma], hn[ma], Un[mb],
-                                                    hn[mb], ge.x, ge.y, ge.w, di, a.g, a.eps, f);
+            const bool ok = limiter_features<T, T4>(Uc, Um, hm, Ua, ha, Ub, hb, ge.x, ge.y, ge.w, di,
+                                                    a.g, a.eps, f);
 #pragma unroll
             for (int i = 0; i < kMlpIn; ++i) X[wv][3 * lane + m][i] = bf16_bits_hw(f[i]);
             // column 14 is padding; column 15 (zero weights) flags an eligible half-edge
