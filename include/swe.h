@@ -174,7 +174,8 @@ const char *swe_strerror(int code);
 int swe_mesh_upload(swe_ctx *ctx, const swe_mesh *mesh);
 
 /* Inflow hydrograph Q(t), piecewise linear through n points (clamped at the
- * ends), evaluated at each stage's time.  n = 0 restores the constant Q. */
+ * ends), evaluated at each stage's time.  n = 0 restores the constant Q.
+ * Waits for the context's stream (the series buffers are replaced). */
 int swe_set_bc_series(swe_ctx *ctx, int n, const double *t, const double *q);
 
 /* State of all n_total cells in the context's precision (float or double),

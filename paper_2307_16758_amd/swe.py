@@ -8,8 +8,10 @@ library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -320,6 +322,17 @@ def _ptr(a, where):
     return C.c_void_p(a.ctypes.data)
 
 
+# contexts whose buffers come from PyTorch's allocator: destroyed at exit
+# while torch is still there to take the buffers back
+_torch_backed = weakref.WeakSet()
+
+
+@atexit.register
+def _close_torch_backed():
+    for s in list(_torch_backed):
+        s.close()
+
+
 def torch_allocator(device=0, stream=None):
     """(alloc, free) callbacks of the context configuration that take the
     context's device buffers from PyTorch's caching allocator, associated
@@ -362,6 +375,8 @@ class Solver:
         _check(_lib.swe_create(C.byref(self.cfg), C.byref(h)))
         self.ctx = h
         self.mesh = None
+        if self._alloc_cbs is not None:
+            _torch_backed.add(self)
 
     def close(self):
         if getattr(self, "ctx", None):
