@@ -106,9 +106,11 @@ typedef struct {
     double eps;        /* wet/dry threshold [m], default 1e-6 */
     double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
     int block;         /* threads per block = cells per tile: 64, 128, 256 or 512 (0: 256);
-                          the one-thread-per-cell kernel and FP64 use at most 256 */
+                          the one-thread-per-cell kernel, FP64 and WAF use at most 256
+                          (FP64 WAF tiles at most 128) */
     int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the
-                          tiled kernel for HLLC1 and MUSCL (WAF always uses the cell kernel) */
+                          tiled kernels (HLLC1, MUSCL, and WAF with Euler steps; WAF with
+                          RK2 uses the cell kernel) */
     void *stream;      /* NULL: the context creates its own stream (default priority,
                           non-blocking); else a hipStream_t on `device`, borrowed: all of
                           the context's work goes to it and it is never destroyed */

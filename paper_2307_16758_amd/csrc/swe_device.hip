@@ -922,6 +922,239 @@ k_stage_tiled(StageArgs<T> a)
     }
 }
 
+// Tiled WAF stage (Euler).  The tiling of k_stage_tiled with WAF's data:
+//  1. every thread stores, per interior half-edge of its cell, the
+//     first-order interface values (h, b, u_n, u_t in its own edge frame),
+//     the cell's eta and tangential velocity and the mean eta and
+//     tangential velocity of its two upwind cells (WAF's ratios,
+//     Sec. 6.2.2), and files the edge tasks as k_stage_tiled does; the
+//     cell's step goes to LDS too (the Courant numbers need it);
+//  2. one dense sweep over the tasks: hydrostatic reconstruction, WAF in the
+//     canonical orientation (operands selected, one evaluation; an edge
+//     leaving the tile recomputes the far side from its 2-ring), rotation
+//     back, each side's share with its side correction (printed form);
+//  3. cell sums, update, Manning, cleanup, CFL commit.
+// Tangential velocities taken in a cell's own frame are negated when that
+// frame is opposite to the canonical one (exact), so an edge gets the same
+// operands, and the same flux bits, wherever it is evaluated.
+template <typename T, int WAFM, int TILE>
+__global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
+{
+    using T4 = typename V4<T>::type;
+    static_assert(TILE <= 1024, "10-bit tile-local indices in task entries");
+    __shared__ T4 sR[3 * TILE];        // own-frame h, b, u_n, u_t
+    __shared__ T4 sQ[3 * TILE];        // eta, u_t (tangential form) of the cell; same of its upwind mean
+    __shared__ unsigned char sH[3 * TILE];  // the half-edge has an upwind cell
+    __shared__ unsigned sTask[3 * TILE];
+    __shared__ int sK[3 * TILE];
+    __shared__ unsigned sW[TILE];
+    __shared__ T sDt[TILE];
+    __shared__ int sCount[2];
+    __shared__ CflVal<T> sCfl[TILE / 64];
+    clock_upkeep(a);
+    const T g = a.g, eps = a.eps;
+    const int ntiles = (a.n + TILE - 1) / TILE;
+    for (int tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+        const int c0 = tile * TILE, cl = threadIdx.x, c = c0 + cl;
+        const bool active = c < a.n;
+        if (threadIdx.x < 2) sCount[threadIdx.x] = 0;
+        __syncthreads();
+        // ---- 1
+        int4 nb4 = make_int4(-1, -1, -1, 0);
+        if (active) nb4 = ldx(a.nbr, c);
+        const DtPrefetch dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur,
+                                           active ? (int)((unsigned)nb4.w >> kScenShift) : -1, a.dt_fixed);
+        T4 Ukeep;
+        const unsigned word = (unsigned)nb4.w;
+        if (active) {
+            const T4 Uc = ldx(a.Uin, c);
+            Ukeep = Uc;
+            sW[cl] = word;
+            const bool hn0 = nb4.x >= 0, hn1 = nb4.y >= 0, hn2 = nb4.z >= 0;
+            const T4 Un0 = a.Uin[hn0 ? nb4.x : c], Un1 = a.Uin[hn1 ? nb4.y : c], Un2 = a.Uin[hn2 ? nb4.z : c];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const int k = m == 0 ? nb4.x : (m == 1 ? nb4.y : nb4.z);
+                sK[m * TILE + cl] = k;
+                const unsigned jb = (word >> (2 * m)) & 3u, isL = (word >> (6 + m)) & 1u;
+                const unsigned ent = (unsigned)m | ((unsigned)cl << 2) | (jb << 12) | (isL << 14);
+                if (k < 0) {
+                    sTask[atomicAdd(&sCount[0], 1)] = ent;
+                    continue;
+                }
+                const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+                const T4 Ua = ma == 0 ? Un0 : (ma == 1 ? Un1 : Un2);
+                const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
+                const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
+                const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
+                const T4 ge = a.he_geo[3 * c + m];
+                T4 rv;
+                rv.x = Uc.x;
+                rv.y = Uc.w;
+                frame_vel(Uc, ge.x, ge.y, eps, rv.z, rv.w);
+                sR[m * TILE + cl] = rv;
+                T eu, vu;
+                const bool hu = waf_upwind(Ua, ha, Ub, hb, ge.x, ge.y, eps, eu, vu);
+                T4 q;
+                q.x = Uc.x + Uc.w;
+                q.y = tangential(Uc, ge.x, ge.y, eps);
+                q.z = eu;
+                q.w = vu;
+                sQ[m * TILE + cl] = q;
+                sH[m * TILE + cl] = hu ? 1 : 0;
+                const int kl = k - c0;
+                if (kl >= 0 && kl < TILE) {
+                    if (isL) sTask[3 * TILE - 1 - atomicAdd(&sCount[1], 1)] = ent | ((unsigned)kl << 15);
+                } else {
+                    sTask[atomicAdd(&sCount[0], 1)] = ent;
+                }
+            }
+        }
+        const int s = active ? (int)(word >> kScenShift) : -1;
+        const double dtd = dt_finish(dtp, a.clock, a.ncopy, a.slot_cur, s, a.cfl_rule, a.cfl,
+                                     a.dt_max, a.dt_fixed);
+        sDt[cl] = T(dtd);
+        __syncthreads();
+        // ---- 2
+        {
+            const int n0 = sCount[0], nt = n0 + sCount[1];
+            for (int i = threadIdx.x; i < nt; i += TILE) {
+                const bool inside = i >= n0;
+                const unsigned task = inside ? sTask[3 * TILE - 1 - (i - n0)] : sTask[i];
+                const int m = task & 3u, tl = (task >> 2) & 1023u, jb = (task >> 12) & 3u;
+                const bool isL = (task >> 14) & 1u;
+                const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
+                const int tc = c0 + tl;
+                const int k = inside ? c0 + kl : sK[m * TILE + tl];
+                const T4 ge = a.he_geo[3 * tc + m];
+                const T nx = ge.x, ny = ge.y;
+                if (k < 0) {  // boundary flux (Sec. 6.1), printed form, global frame
+                    const T4 Ut = ldx(a.Uin, tc);
+                    const int st = (int)(sW[tl] >> kScenShift);
+                    const ScenParams sp = a.scen[st];
+                    const T q_in = k == kBcInflow
+                                       ? T(inflow_at(sp, a.ser_t, a.ser_q,
+                                                     bitsd(a.clock[clock_off(a.ncopy, st, a.slot_cur)])) *
+                                           sp.inv_inflow_len)
+                                       : T(0);
+                    T G[3];
+                    boundary_flux<T, T4>(k, Ut, nx, ny, g, eps, q_in, T(sp.outflow_stage), G);
+                    T4 fb;
+                    fb.x = G[0]; fb.y = G[1]; fb.z = G[2]; fb.w = T(0);
+                    sR[m * TILE + tl] = fb;
+                    continue;
+                }
+                const T4 ov = sR[m * TILE + tl], oq = sQ[m * TILE + tl];
+                const bool oh = sH[m * TILE + tl] != 0;
+                T4 kv, kq;
+                bool kh;
+                if (inside) {
+                    kv = sR[jb * TILE + kl];
+                    kq = sQ[jb * TILE + kl];
+                    kh = sH[jb * TILE + kl] != 0;
+                } else {
+                    // far side from its 2-ring, in its own frame (normal -n)
+                    const T4 Uk = ldx(a.Uin, k);
+                    const int4 nk = ldx(a.nbr, k);
+                    const int ka = pick3(nk, (jb + 1) % 3), kb = pick3(nk, (jb + 2) % 3);
+                    const T4 Uka = a.Uin[ka >= 0 ? ka : k], Ukb = a.Uin[kb >= 0 ? kb : k];
+                    kv.x = Uk.x;
+                    kv.y = Uk.w;
+                    frame_vel(Uk, -nx, -ny, eps, kv.z, kv.w);
+                    T eu, vu;
+                    kh = waf_upwind(Uka, ka >= 0, Ukb, kb >= 0, -nx, -ny, eps, eu, vu);
+                    kq.x = Uk.x + Uk.w;
+                    kq.y = tangential(Uk, -nx, -ny, eps);
+                    kq.z = eu;
+                    kq.w = vu;
+                }
+                // hydrostatic reconstruction (first-order states)
+                const T be = tmax(ov.y, kv.y);
+                const T hso = tmax(T(0), ov.x + ov.y - be);
+                const T hsk = tmax(T(0), kv.x + kv.y - be);
+                // canonical orientation: L's own frame is the canonical one,
+                // R's is opposite (its normal and tangential components flip)
+                const T4 &Lv = isL ? ov : kv, &Rv = isL ? kv : ov, &Lq = isL ? oq : kq, &Rq = isL ? kq : oq;
+                const T hL = isL ? hso : hsk, hR = isL ? hsk : hso;
+                T UL[3], UR[3];
+                UL[0] = hL; UL[1] = hL * Lv.z; UL[2] = hL * Lv.w;
+                UR[0] = hR; UR[1] = -(hR * Rv.z); UR[2] = -(hR * Rv.w);
+                WafIn<T> w;
+                w.eL = Lq.x; w.eR = Rq.x;
+                w.vL = Lq.y; w.vR = -Rq.y;
+                w.eLu = Lq.z; w.eRu = Rq.z;
+                w.vLu = Lq.w; w.vRu = -Rq.w;
+                w.hasLu = isL ? oh : kh;
+                w.hasRu = isL ? kh : oh;
+                T F[3];
+                flux_waf<T, WAFM>(g, eps, fdiv(sDt[tl], a.he_dist[3 * tc + m].w), UL, UR, w, F);
+                const T sg = isL ? T(1) : T(-1);
+                const T nLx = sg * nx, nLy = sg * ny;
+                const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
+                T4 fo;
+                half_edge_flux(sg, G0, G1, G2, T(0.5) * g * (ov.x * ov.x - hso * hso), nx, ny, fo.x,
+                               fo.y, fo.z);
+                fo.w = T(0);
+                sR[m * TILE + tl] = fo;
+                if (inside) {
+                    T4 fk;
+                    half_edge_flux(-sg, G0, G1, G2, T(0.5) * g * (kv.x * kv.x - hsk * hsk), -nx, -ny,
+                                   fk.x, fk.y, fk.z);
+                    fk.w = T(0);
+                    sR[jb * TILE + kl] = fk;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3
+        CflVal<T> cfl = cfl_none<T>();
+        if (active) {
+            const T4 Uc = Ukeep;
+            const T dt = sDt[cl];
+            T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const T lam = ldx(a.he_lam, m * a.n + c);
+                const T4 f = sR[m * TILE + cl];
+                acc0 += lam * f.x;
+                acc1 += lam * f.y;
+                acc2 += lam * f.z;
+            }
+            T nh = Uc.x - dt * acc0;
+            T nu = Uc.y - dt * acc1;
+            T nv = Uc.z - dt * acc2;
+            const T4 cg = ldx(a.cell, c);
+            int flags = 0;
+            if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
+            if (nh < T(0)) {
+                flags |= nh < -eps ? kHealthNegDepth : kHealthClipped;
+                nh = T(0);
+            }
+            if (nh <= eps) {
+                nu = T(0); nv = T(0);
+            } else if (cg.z > T(0)) {  // Manning, point-implicit
+                const T sp = sqrt(nu * nu + nv * nv) * frcp(nh);
+                const T f = T(1) + dt * g * cg.z * sp * pow_m43(nh);
+                const T rf = frcp(f);
+                nu *= rf; nv *= rf;
+            }
+            T4 out;
+            out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
+            stx(a.Uout, c, out);
+            if (flags) atomicOr(a.health, flags);
+            cfl.scen = s;
+            if (((word >> kOwnedBit) & 1u) && nh > eps) {
+                const T r = frcp(nh);
+                const T u = nu * r, v = nv * r;
+                const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
+                cfl = cfl_cell<T>(a.cfl_rule, s, cg.y, lm);
+            }
+        }
+        cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, cfl, sCfl);
+        if (tile + (int)gridDim.x < ntiles) __syncthreads();
+    }
+}
+
 // CFL minima of the current state into one clock slot (after set_state).
 template <typename T>
 __global__ void __launch_bounds__(256) k_cfl_init(int n, const int4 *nbr,
@@ -1171,9 +1404,21 @@ template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm
 
 // Stage kernel of a configuration: the tiled kernel for first-order HLLC and
 // MUSCL (tile = block size 64, 128 or 256), the cell kernel for WAF.
-template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int block, int cell,
-                                              bool w7)
+template <typename T, int TILE> KernelFn<T> pick_tiled_waf(int wafm)
 {
+    if (wafm == kWafGodunov) return k_stage_tiled_waf<T, kWafGodunov, TILE>;
+    if (wafm == kWafUnlimited) return k_stage_tiled_waf<T, kWafUnlimited, TILE>;
+    return k_stage_tiled_waf<T, kWafSuperbee, TILE>;
+}
+
+template <typename T> KernelFn<T> pick_kernel(int scheme, int lim, int wafm, int block, int cell,
+                                              bool w7, bool euler)
+{
+    if (scheme == kWAF && !cell && euler) {  // tiled WAF: Euler only (as the paper's WAF)
+        if (block == 64) return pick_tiled_waf<T, 64>(wafm);
+        if (block == 128 || sizeof(T) == 8) return pick_tiled_waf<T, 128>(wafm);
+        return pick_tiled_waf<T, 256>(wafm);
+    }
     if (scheme != kWAF && !cell) {
         if (block == 64) return pick_tiled<T, 64>(scheme, lim);
         if (block == 128) return pick_tiled<T, 128>(scheme, lim);
@@ -1233,10 +1478,14 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.slot_reset = (int)((step + 2) % 3);
     // the one-thread-per-cell kernel is built for at most 256 threads, and
     // FP64 tiles stop at 256 cells (LDS)
-    const bool cell_kernel = c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel;
-    const int B = cell_kernel || sizeof(T) == 8 ? std::min(c->block, 256) : c->block;
+    const bool euler = c->cfg.integrator == SWE_EULER;
+    const bool cell_kernel = c->cfg.cell_kernel || (c->cfg.scheme == SWE_WAF && !euler);
+    // the cell kernel, FP64 and the WAF tiles stop at 256 cells (FP64 WAF
+    // tiles at 128: LDS)
+    int B = cell_kernel || sizeof(T) == 8 || c->cfg.scheme == SWE_WAF ? std::min(c->block, 256) : c->block;
+    if (c->cfg.scheme == SWE_WAF && !cell_kernel && sizeof(T) == 8) B = std::min(B, 128);
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B,
-                                   c->cfg.cell_kernel, seven_waves<T>(c, B));
+                                   cell_kernel, seven_waves<T>(c, B), euler);
     const int ntiles = (c->n_total + B - 1) / B;
     const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
     const dim3 blk(B);

@@ -79,10 +79,12 @@ def test_river_muscl_fp32_1000_steps(cell_kernel, block):
     assert max(errs) <= 1e-4, errs
 
 
+@pytest.mark.parametrize("cell_kernel", [0, 1])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-10), (0, 1e-3)])
-def test_dam_break_waf(prec, tol):
+def test_dam_break_waf(prec, tol, cell_kernel):
+    """WAF (superbee weights) on a 2D dam break, tiled and cell kernels."""
     sc = dam_break_channel(Lx=50.0, Ly=10.0, nx=100, ny=20, x_dam=25.0)
-    s, M, par, pr = make_pair(sc, "waf", precision=prec)
+    s, M, par, pr = make_pair(sc, "waf", precision=prec, cell_kernel=cell_kernel)
     l2g = pr.sub.l2g
     dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
     g, r = _run_both(s, M, par, sc, l2g, 60, dt_fixed=dt)
@@ -132,7 +134,7 @@ def test_graph_and_direct_launches_agree_bitwise():
     assert a.time() == b.time()
 
 
-@pytest.mark.parametrize("name", ["hllc1", "muscl_superbee_rk2"])
+@pytest.mark.parametrize("name", ["hllc1", "muscl_superbee_rk2", "waf"])
 def test_tiled_results_do_not_depend_on_tile_size(name):
     """Every edge is evaluated by one code path wherever the tiling puts
     it, so the tiled kernel gives bitwise the same state for every tile
