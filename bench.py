@@ -269,7 +269,8 @@ def main():
                      if (args.limiter == "minmod" and kw["scheme"] == 1 and not args.cell_kernel
                          and not tuned) else None,
                      "kernel": ("autotuned stage kernel" if tuned else
-                                ("k_stage" if args.cell_kernel or kw["scheme"] == 2 else "k_stage_tiled")
+                                ("k_stage" if args.cell_kernel or (kw["scheme"] == 2 and kw["integrator"] == 1)
+                                 else ("k_stage_tiled_waf" if kw["scheme"] == 2 else "k_stage_tiled"))
                                 + (" + k_limiter_phi (per-launch time covers both)"
                                    if args.limiter == "learned" else "")),
                      "avg_launch_us": avg_launch_s * 1e6,
