@@ -129,7 +129,9 @@ typedef struct {
     void *(*alloc)(size_t bytes, void *user);
     void (*free)(void *ptr, void *user);
     void *alloc_user;
-    int reserved[2];
+    double waf_dry;    /* WAF: an edge with a hydrostatic interface depth below this [m]
+                          takes the first-order weights (A = 1, i.e. HLLC); keeps WAF's
+                          depths non-negative at wet/dry fronts.  Default 0.05 */
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).

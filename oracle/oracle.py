@@ -47,7 +47,7 @@ class _Params(C.Structure):
                 ("inflow_len", C.c_double), ("outflow_stage", C.c_double),
                 ("n_series", C.c_int), ("pad", C.c_int),
                 ("series_t", C.POINTER(C.c_double)), ("series_q", C.POINTER(C.c_double)),
-                ("mlp", C.POINTER(C.c_double))]
+                ("mlp", C.POINTER(C.c_double)), ("waf_dry", C.c_double)]
 
 
 class _Sub(C.Structure):
@@ -114,6 +114,7 @@ class Params:
     integrator: int = EULER
     limiter: int = MINMOD
     waf_limiter: int = WAF_SUPERBEE
+    waf_dry: float = 0.05
     cfl_rule: int = 0
     mlp_bf16: int = 0
     inflow_q: float = 0.0
@@ -127,6 +128,7 @@ class Params:
         p = _Params(self.g, self.cfl, self.eps, self.dt_max, self.scheme, self.integrator,
                     self.limiter, self.waf_limiter, self.cfl_rule, self.mlp_bf16,
                     self.inflow_q, self.inflow_len, self.outflow_stage, 0, 0)
+        p.waf_dry = self.waf_dry
         self._keep = []
         if self.hydrograph is not None:
             t = np.ascontiguousarray(self.hydrograph[0], np.float64)

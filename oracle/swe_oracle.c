@@ -44,6 +44,7 @@ typedef struct {
     int n_series, pad;
     const double *series_t, *series_q;
     const double *mlp; /* MLP_NPAR weights, layout of mlp_unpack() */
+    double waf_dry;    /* WAF: an edge with a hydrostatic state shallower than this takes A = 1 */
 } or_params;
 
 typedef struct {
@@ -290,11 +291,14 @@ static double waf_A(int mode, double r, double c)
 
 static void flux_waf(double g, double eps, int mode, double dt_dx, const double UL[3],
                      const double UR[3], const waf_ratio_in *rh, const waf_ratio_in *rv,
-                     double F[3])
+                     double waf_dry, double F[3])
 {
     wave_fan W;
     wave_speeds(g, eps, UL, UR, &W);
     if (W.dry) { F[0] = F[1] = F[2] = 0.0; return; }
+    /* near a wet/dry front (either hydrostatic state shallower than
+     * waf_dry) the edge takes the first-order weights, A = 1 (HLLC) */
+    if (UL[0] < waf_dry || UR[0] < waf_dry) mode = OR_WAF_GODUNOV;
     double cL = W.SL * dt_dx, cR = W.SR * dt_dx, cs = W.Ss * dt_dx;
     double AL = waf_A(mode, waf_ratio(W.SL, rh), cL);
     double AR = waf_A(mode, waf_ratio(W.SR, rh), cR);
@@ -785,7 +789,7 @@ static void stage(or_mesh *M, const or_params *P, const double *h, const double 
                 else if (Ra >= 0) { rh_.qRu = et[2]; rv_.qRu = vt[2]; }
                 else if (Rb >= 0) { rh_.qRu = et[3]; rv_.qRu = vt[3]; }
                 double dx = hypot(M->cx[R] - M->cx[L], M->cy[R] - M->cy[L]);
-                flux_waf(g, eps, P->waf_limiter, dt / dx, UL, UR, &rh_, &rv_, F);
+                flux_waf(g, eps, P->waf_limiter, dt / dx, UL, UR, &rh_, &rv_, P->waf_dry, F);
             } else {
                 flux_hllc(g, eps, UL, UR, F);
             }
@@ -919,7 +923,7 @@ int or_riemann(const or_params *P, int scheme, const double *UL, const double *U
             rv.qL = ratio_in[4]; rv.qR = ratio_in[5]; rv.qLu = ratio_in[6]; rv.qRu = ratio_in[7];
             rh.hasLu = rh.hasRu = rv.hasLu = rv.hasRu = 1;
         }
-        flux_waf(P->g, P->eps, P->waf_limiter, dt_dx, UL, UR, &rh, &rv, F);
+        flux_waf(P->g, P->eps, P->waf_limiter, dt_dx, UL, UR, &rh, &rv, P->waf_dry, F);
     } else {
         flux_hllc(P->g, P->eps, UL, UR, F);
     }

@@ -336,6 +336,7 @@ template <typename T> struct StageArgs {
     const float *phi;
     int *health;
     T g, eps;
+    T waf_dry;  // WAF: first-order weights where a hydrostatic state is shallower
     double cfl, dt_max, dt_fixed;
     int slot_cur, slot_next, slot_reset;
     int kind;  // 0: Euler step, 1: first RK2 stage, 2: second RK2 stage (+ average)
@@ -578,7 +579,7 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
                 const bool hk = waf_upwind(Uka, hka, Ukb, hkb, nLx, nLy, eps, ek, vk);
                 if (isL) { w.eLu = eo; w.vLu = vo; w.hasLu = ho; w.eRu = ek; w.vRu = vk; w.hasRu = hk; }
                 else { w.eLu = ek; w.vLu = vk; w.hasLu = hk; w.eRu = eo; w.vRu = vo; w.hasRu = ho; }
-                flux_waf<T, WAFM>(g, eps, fdiv(dt, dw.w), UL, UR, w, F);
+                flux_waf<T, WAFM>(g, eps, fdiv(dt, dw.w), UL, UR, w, a.waf_dry, F);
             } else {
                 flux_hllc(g, eps, UL, UR, F);
             }
@@ -1087,7 +1088,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 w.hasLu = isL ? oh : kh;
                 w.hasRu = isL ? kh : oh;
                 T F[3];
-                flux_waf<T, WAFM>(g, eps, fdiv(sDt[tl], a.he_dist[3 * tc + m].w), UL, UR, w, F);
+                flux_waf<T, WAFM>(g, eps, fdiv(sDt[tl], a.he_dist[3 * tc + m].w), UL, UR, w, a.waf_dry, F);
                 const T sg = isL ? T(1) : T(-1);
                 const T nLx = sg * nx, nLy = sg * ny;
                 const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
@@ -1469,6 +1470,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     a.health = c->health;
     a.g = T(c->cfg.g);
     a.eps = T(c->cfg.eps);
+    a.waf_dry = T(c->cfg.waf_dry);
     a.cfl = c->cfg.cfl;
     a.dt_max = c->cfg.dt_max;
     a.dt_fixed = dt_fixed;
@@ -1541,6 +1543,7 @@ void swe_config_default(swe_config *cfg)
     cfg->cfl = 0.45;
     cfg->eps = 1e-6;
     cfg->dt_max = 0.0;
+    cfg->waf_dry = 0.05;
 }
 
 const char *swe_strerror(int code)
@@ -1570,7 +1573,7 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
-        !(cfg->eps >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+        !(cfg->eps >= 0) || !(cfg->waf_dry >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
         (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7) || (!cfg->alloc != !cfg->free))

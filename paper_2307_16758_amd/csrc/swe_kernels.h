@@ -267,17 +267,20 @@ template <typename T> struct WafIn {
     bool hasLu, hasRu;
 };
 
+// WAF flux; near a wet/dry front (a hydrostatic state shallower than
+// `shallow`) the first-order weights A = 1, i.e. HLLC.
 template <typename T, int MODE>
 __device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], const T UR[3],
-                                         const WafIn<T> &w, T F[3])
+                                         const WafIn<T> &w, T shallow, T F[3])
 {
     Fan<T> W;
     wave_fan(g, eps, UL, UR, W);
     if (W.dry) { F[0] = F[1] = F[2] = T(0); return; }
     const T cL = W.SL * dt_dx, cR = W.SR * dt_dx, cs = W.Ss * dt_dx;
-    const T AL = waf_A<T, MODE>(waf_ratio(W.SL, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cL);
-    const T AR = waf_A<T, MODE>(waf_ratio(W.SR, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cR);
-    const T As = waf_A<T, MODE>(waf_ratio(W.Ss, w.vL, w.vR, w.vLu, w.vRu, w.hasLu, w.hasRu), cs);
+    const bool first = UL[0] < shallow || UR[0] < shallow;
+    const T AL = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.SL, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cL);
+    const T AR = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.SR, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cR);
+    const T As = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.Ss, w.vL, w.vR, w.vLu, w.vRu, w.hasLu, w.hasRu), cs);
     const T wL = T(0.5) * (T(1) + sgn(cL) * AL);
     const T wLR = T(0.5) * (sgn(cR) * AR - sgn(cL) * AL);
     const T wR = T(0.5) * (T(1) - sgn(cR) * AR);

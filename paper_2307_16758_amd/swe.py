@@ -70,7 +70,7 @@ class swe_config(C.Structure):
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
                 ("block", C.c_int), ("cell_kernel", C.c_int), ("stream", C.c_void_p),
                 ("waves", C.c_int), ("reserved0", C.c_int), ("alloc", ALLOC_FN),
-                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("reserved", C.c_int * 2)]
+                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("waf_dry", C.c_double)]
 
 
 class swe_mesh(C.Structure):

@@ -38,7 +38,7 @@ def make_pair(sc, name, precision, P=1, p=0, k=0, prepared=None, **cfg):
     M = O.Mesh(sc.mesh.xy, sc.mesh.tri[l2g], pr.sub.nbr, sc.b[l2g], sc.manning[l2g],
                gid=l2g, n_owned=pr.sub.n_owned)
     okw = {k_: v for k_, v in kw.items() if k_ in ("scheme", "integrator", "limiter")}
-    for k_ in ("waf_limiter", "cfl_rule", "cfl", "dt_max", "eps"):
+    for k_ in ("waf_limiter", "waf_dry", "cfl_rule", "cfl", "dt_max", "eps"):
         if k_ in cfg:
             okw[k_] = cfg[k_]
     par = O.scenario_params(sc, **okw)

@@ -122,7 +122,10 @@ def test_dam_break_onto_dry_bed(name):
     g = s.read_state()
     r = _oracle_run(M, par, sc, pr.sub.l2g, 150)
     errs = state_errors(g, r[:3], pr.sub.n_owned)
-    assert max(errs) <= 1e-10, errs
+    # WAF switches discretely (its superbee ratio, and the first-order
+    # weights below waf_dry at the front): a rounding-order difference can
+    # pick other weights at an isolated edge, so it gets 1e-9
+    assert max(errs) <= (1e-9 if name == "waf" else 1e-10), errs
     A = M.geometry()["area"]
     m0 = (A * sc.h[pr.sub.l2g]).sum()
     assert abs((A * g[0]).sum() - m0) <= 1e-12 * m0

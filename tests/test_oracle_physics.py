@@ -194,6 +194,22 @@ def test_closed_cell_friction_decay(name, kw):
     assert math.isclose(hu[0] * v0, hv[0] * u0, rel_tol=1e-12)
 
 
+def test_waf_stays_non_negative_at_wet_dry_fronts():
+    """WAF with the first-order fallback at edges whose hydrostatic state is
+    shallower than waf_dry keeps the river's depths non-negative (dry banks,
+    bumps, inflow); without it (waf_dry = 0) the superbee weights drive a
+    shoreline cell below zero within a few hundred steps."""
+    sc = river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=2)
+    M, _ = O.global_mesh(sc)
+    flags = {}
+    for dry in (0.05, 0.0):
+        p = O.scenario_params(sc, scheme=O.WAF, integrator=O.EULER, waf_dry=dry)
+        h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 1500)
+        flags[dry] = fl
+    assert flags[0.05] == 0
+    assert flags[0.0] & 2                  # a depth below -eps
+
+
 def test_all_dry_domain():
     """No wet cell: no CFL step exists; with dt_max the state stays exactly
     dry and the clock advances by dt_max per step."""
