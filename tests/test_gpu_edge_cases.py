@@ -132,6 +132,24 @@ def test_dam_break_onto_dry_bed(name):
     assert (g[0] > 0).sum() > (sc.h > 0).sum()          # the front has advanced
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_waf_on_a_river_stays_non_negative(prec):
+    """WAF on a river with dry banks, bumps and inflow for 1500 CFL steps:
+    with the first-order weights below waf_dry at the fronts no depth goes
+    below -eps (the library would report NEGATIVE_DEPTH), and the state
+    tracks the oracle's over the first steps."""
+    sc = river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=2)
+    s, M, par, pr = make_pair(sc, "waf", precision=prec)
+    s.step(20)
+    g = s.read_state()
+    r = _oracle_run(M, par, sc, pr.sub.l2g, 20)
+    errs = _vector_errors(g, r, pr.sub.n_owned)
+    assert max(errs) <= (1e-9 if prec == 1 else 1e-4), errs
+    s.step(1480)
+    h, _, _ = s.read_state()
+    assert s.health() == 0 and h.min() >= 0.0
+
+
 def _bare_mesh(n_total, n_nodes=3):
     """A mesh struct that declares sizes only (every array pointer NULL)."""
     swe, _ = lib()
