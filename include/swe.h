@@ -220,7 +220,14 @@ int swe_step(swe_ctx *ctx, int n_steps, double dt_fixed);
 
 int swe_sync(swe_ctx *ctx);                 /* wait + report health */
 int swe_time(swe_ctx *ctx, double *t);      /* simulated time (syncs) */
-int swe_local_dt(swe_ctx *ctx, double *dt); /* CFL step of the current state (syncs) */
+/* CFL step of the current state over the owned cells (syncs): the step
+ * swe_step takes in CFL mode.  A sub-domain without a wet owned cell gives
+ * dt_max, or 0 when none is configured (no bound from this part).
+ * Sub-domains combine by a minimum (a min all-reduce) with cfl_rule 0:
+ * each contributes +inf for 0, and an infinite result means no wet cell
+ * anywhere (step 0, as one context would).  With cfl_rule 1 the global
+ * step is not the minimum of the parts' steps. */
+int swe_local_dt(swe_ctx *ctx, double *dt);
 int swe_health(swe_ctx *ctx, int *bits);    /* SWE_HEALTH_* bits since the last set_state */
 
 /* Gather the owned cells listed in send_idx into dev_sendbuf, laid out
