@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--limiter", choices=("minmod", "learned"), default="minmod",
                     help="learned: the per-edge network (untrained weights: its cost, not its "
                          "accuracy) ahead of every stage")
+    ap.add_argument("--snapshot-every", type=int, default=0, metavar="M",
+                    help="take the state to pinned host memory every M steps (swe_snapshot, "
+                         "copied on a side stream while the steps go on), inside the timed region")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for the HBM byte counters)")
@@ -209,8 +212,13 @@ def main():
 
     tuned = s.autotune(10) if args.autotune else None
     s.step(args.warmup)
+    if args.snapshot_every > 0:
+        # staging slots, side stream and pinned pool are set up by the first
+        # snapshots: part of the warm-up, like the kernels' first launches
+        for _ in range(3):
+            s.snapshot().wait()
     s.sync()
-    if sendbuf is not None:
+    if sendbuf is not None or args.snapshot_every > 0:
         # the stage kernel alone (HIP events on the library stream), for the
         # roofline; the state moves on, which the timed job below does not mind
         s.step(args.steps)
@@ -218,7 +226,17 @@ def main():
         gpu_ms = s.last_step_ms()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if sendbuf is None:
+    if args.snapshot_every > 0:
+        snaps, done = [], 0
+        while done < args.steps:
+            m = min(args.snapshot_every, args.steps - done)
+            s.step(m)
+            done += m
+            snaps = snaps[-1:] + [s.snapshot()]   # older ones are complete (two slots)
+        s.sync()
+        for x in snaps:
+            x.wait()
+    elif sendbuf is None:
         s.step(args.steps)
         s.sync()
         gpu_ms = s.last_step_ms()       # HIP events around the timed steps, library stream
@@ -259,7 +277,9 @@ def main():
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
                                f"{'MUSCL-HLLC-RK2' if rk2 else ('WAF' if kw['scheme'] == 2 else 'HLLC') + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
-                               + (f", part of {P} with {k} ghost layers + pack" if P > 1 else ""),
+                               + (f", part of {P} with {k} ghost layers + pack" if P > 1 else "")
+                               + (f", snapshot to host every {args.snapshot_every} steps"
+                                  if args.snapshot_every > 0 else ""),
                    "cells": n_owned, "tuned_launch": tuned,
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

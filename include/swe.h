@@ -189,6 +189,17 @@ int swe_set_state(swe_ctx *ctx, const void *h, const void *hu, const void *hv, i
                   double t);
 int swe_read_state(swe_ctx *ctx, void *h, void *hu, void *hv, int where);
 
+/* Solution output that overlaps the steps (Sec. 5.2: solutions written
+ * while the solver keeps computing, the table of write modes): queues on the context's stream a copy of the state of all
+ * n_total cells, as it stands after the steps queued so far, into three
+ * device buffers of n_total values each in the context's precision, then
+ * records done_event (a hipEvent_t, may be NULL) on that stream.  Returns
+ * without waiting and without reporting health, so a copy to host memory
+ * on another stream after done_event overlaps the following steps.
+ * SWE_ERR_ARG if a buffer is not device memory of the context's device;
+ * the buffers must not be reused before done_event has completed. */
+int swe_snapshot(swe_ctx *ctx, void *h, void *hu, void *hv, void *done_event);
+
 /* Batched ensemble: several independent meshes (no ghost cells), one
  * scenario each, concatenated in one context and stepped together by the
  * same kernel launches (one graph), each scenario with its own CFL step,

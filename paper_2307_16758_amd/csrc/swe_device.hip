@@ -1898,6 +1898,40 @@ int swe_read_state(swe_ctx *c, void *h, void *hu, void *hv, int where)
     return health_status(c);
 }
 
+// true if p is device (or managed) memory of the context's device; a failed
+// query leaves HIP's last error set, which is cleared here so that the next
+// launch check does not report it
+static bool device_buffer(const swe_ctx *c, const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == c->dev;
+}
+
+int swe_snapshot(swe_ctx *c, void *h, void *hu, void *hv, void *done_event)
+{
+    if (!c || !h || !hu || !hv) return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
+    HIP_OK(c, hipSetDevice(c->dev));
+    if (!device_buffer(c, h) || !device_buffer(c, hu) || !device_buffer(c, hv))
+        return set_err(c, SWE_ERR_ARG, "snapshot buffers must be device memory of the context's device");
+    const size_t n = c->n_total;
+    const int B = 256, G = (int)((n + B - 1) / B);
+    void *Ucur = c->U[c->step_count & 1];
+    if (c->tsize == 8)
+        hipLaunchKernelGGL(k_unpack_state<double>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const double4 *)Ucur, (double *)h, (double *)hu, (double *)hv);
+    else
+        hipLaunchKernelGGL(k_unpack_state<float>, dim3(G), dim3(B), 0, c->stream, (int)n,
+                           (const float4 *)Ucur, (float *)h, (float *)hu, (float *)hv);
+    HIP_OK(c, hipGetLastError());
+    if (done_event) HIP_OK(c, hipEventRecord((hipEvent_t)done_event, c->stream));
+    return SWE_OK;
+}
+
 int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
 {
     if (!c || n_steps < 0) return set_err(c, SWE_ERR_ARG, "bad argument");

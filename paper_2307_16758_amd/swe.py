@@ -107,6 +107,7 @@ _sig("swe_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
                                 C.c_double])
 _sig("swe_read_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int])
 _sig("swe_step", C.c_int, [C.c_void_p, C.c_int, C.c_double])
+_sig("swe_snapshot", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("swe_mesh_upload_batch", C.c_int, [C.c_void_p, C.c_int, C.POINTER(swe_mesh)])
 _sig("swe_set_bc_series_scenario", C.c_int, [C.c_void_p, C.c_int, C.c_int, f64p, f64p])
 _sig("swe_batch_offsets", C.c_int, [C.c_void_p, i32p, i32p])
@@ -144,7 +145,7 @@ _sig("swe_subdomain_free", None, [C.c_void_p])
 
 EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error", "swe_strerror",
             "swe_mesh_upload", "swe_set_bc_series", "swe_set_state", "swe_read_state",
-            "swe_step", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
+            "swe_snapshot", "swe_step", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
             "swe_batch_offsets", "swe_scenario_times", "swe_autotune", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
             "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
             "swe_limiter_set_weights", "swe_limiter_phi", "swe_limiter_pairs",
@@ -351,6 +352,22 @@ def torch_allocator(device=0, stream=None):
     return ALLOC_FN(_alloc), FREE_FN(_free)
 
 
+class Snapshot:
+    """A state on its way to pinned host memory (Solver.snapshot)."""
+
+    def __init__(self, host, done):
+        self._host, self._done = host, done
+
+    def ready(self):
+        return self._done.query()
+
+    def wait(self):
+        """(h, hu, hv) as numpy arrays over the pinned buffer."""
+        self._done.synchronize()
+        a = self._host.numpy()
+        return a[0], a[1], a[2]
+
+
 class Solver:
     """One swe_ctx: a sub-domain (or a whole mesh) on one GPU."""
 
@@ -455,6 +472,43 @@ class Solver:
             where = DEVICE if hasattr(out[0], "data_ptr") else HOST
         self._chk(_lib.swe_read_state(self.ctx, *(_ptr(a, where) for a in out), where))
         return out
+
+    def snapshot(self, side_stream=None):
+        """The state as it stands after the steps queued so far, copied to
+        pinned host memory on side_stream (a torch.cuda.Stream; one per
+        context by default) while the following steps run: swe_snapshot
+        into one of two device staging slots, then a copy on the side
+        stream.  Returns a Snapshot; its wait() gives (h, hu, hv)."""
+        import torch
+        dev = torch.device("cuda", self.cfg.device)
+        n = self.mesh.n_total
+        if getattr(self, "_snap", None) is None:
+            tdt = torch.float64 if self.dtype == np.float64 else torch.float32
+            slots = [torch.empty((3, n), dtype=tdt, device=dev) for _ in range(2)]
+            # the context's stream is not ordered after torch's: let any
+            # earlier torch work on the recycled memory finish first
+            torch.cuda.current_stream(dev).synchronize()
+            self._snap = dict(slots=slots, done=[None, None], next=0,
+                              side=torch.cuda.Stream(dev))
+        st = self._snap
+        side = side_stream if side_stream is not None else st["side"]
+        i = st["next"]
+        st["next"] = 1 - i
+        if st["done"][i] is not None:
+            st["done"][i].synchronize()       # the slot's previous copy has left
+        buf = st["slots"][i]
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream(dev))   # creates the event; re-recorded below
+        self._chk(_lib.swe_snapshot(self.ctx, *(C.c_void_p(buf[f].data_ptr()) for f in range(3)),
+                                    C.c_void_p(ready.cuda_event)))
+        host = torch.empty(buf.shape, dtype=buf.dtype, pin_memory=True)
+        side.wait_event(ready)
+        with torch.cuda.stream(side):
+            host.copy_(buf, non_blocking=True)
+        done = torch.cuda.Event()
+        done.record(side)
+        st["done"][i] = done
+        return Snapshot(host, done)
 
     def step(self, n_steps, dt_fixed=0.0):
         self._chk(_lib.swe_step(self.ctx, int(n_steps), float(dt_fixed)))
