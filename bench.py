@@ -70,13 +70,15 @@ def workload(name):
 
 
 def kernel_source_hash():
-    """sha256 of the device sources: a traffic figure measured on other
-    sources does not describe the present kernel."""
+    """sha256 of the device sources (the .hip files and the headers they
+    include; the host toolkit, .cpp built by g++, holds no device code): a
+    traffic figure measured on other sources does not describe the present
+    kernel."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2307_16758_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h", ".cpp")):
+        if f.endswith((".hip", ".h")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()

@@ -54,7 +54,7 @@ extern "C" {
 #define SWE_ERR_NONFINITE -4      /* a NaN/Inf appeared in the state while stepping */
 #define SWE_ERR_NEGATIVE_DEPTH -5 /* a depth below -eps appeared while stepping */
 #define SWE_ERR_DEVICE -6         /* HIP runtime error */
-#define SWE_ERR_OOM -7            /* device allocation failed */
+#define SWE_ERR_OOM -7            /* an allocation failed (device; host in the toolkit) */
 #define SWE_ERR_UNSUPPORTED -8    /* option not available in this build */
 
 /* enums */
@@ -326,6 +326,16 @@ int swe_subdomain_build(int32_t n_nodes, const double *node_xy, int32_t n_cells,
                         const int32_t *cell_nodes, const int32_t *nbr, const int8_t *bc,
                         const int32_t *part, int32_t P, int32_t p, int32_t k,
                         swe_subdomain **out);
+/* All P parts at once on n_threads host threads (<= 0: one per hardware
+ * thread), out[P]: each part equals what swe_subdomain_build gives for it
+ * (Sec. 3: ghost layers of every sub-domain generated in parallel; here the
+ * parts of one shared-memory mesh are built concurrently).  On an error
+ * every out[p] is NULL and the first error is returned; SWE_ERR_OOM when an
+ * allocation fails.  The caller frees each part with swe_subdomain_free. */
+int swe_subdomain_build_all(int32_t n_nodes, const double *node_xy, int32_t n_cells,
+                            const int32_t *cell_nodes, const int32_t *nbr, const int8_t *bc,
+                            const int32_t *part, int32_t P, int32_t k, int32_t n_threads,
+                            swe_subdomain **out);
 typedef struct {
     int32_t n_owned, n_total, n_peers, n_send;
     const int32_t *l2g;       /* [n_total] global id of each local cell */

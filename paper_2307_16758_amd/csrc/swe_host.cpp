@@ -6,12 +6,15 @@
 // Built with -ffp-contract=off so that the Morton quantisation and the
 // geometry are the plain double-precision expressions written here.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <limits>
 #include <numeric>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "swe_internal.h"
@@ -293,6 +296,50 @@ int swe_subdomain_build(int32_t n_nodes, const double *xy, int32_t n, const int3
     }
     S->n_send = (int32_t)S->send_idx.size();
     *out = S;
+    return SWE_OK;
+}
+
+int swe_subdomain_build_all(int32_t n_nodes, const double *xy, int32_t n, const int32_t *tri,
+                            const int32_t *nbr, const int8_t *bc, const int32_t *part, int32_t P,
+                            int32_t k, int32_t n_threads, swe_subdomain **out)
+{
+    if (!out || P <= 0) return SWE_ERR_ARG;
+    for (int32_t p = 0; p < P; ++p) out[p] = nullptr;
+    if (n_threads <= 0) n_threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
+    n_threads = std::min(n_threads, P);
+    // parts are independent given the dual graph and the partition: each
+    // worker claims the next part and builds it exactly as a single call does
+    std::atomic<int32_t> next{0};
+    std::atomic<int> status{SWE_OK};
+    auto work = [&]() {
+        for (int32_t p = next++; p < P && status.load() == SWE_OK; p = next++) {
+            int rc;
+            try {
+                rc = swe_subdomain_build(n_nodes, xy, n, tri, nbr, bc, part, P, p, k, &out[p]);
+            } catch (const std::bad_alloc &) {
+                rc = SWE_ERR_OOM;
+            }
+            if (rc != SWE_OK) {
+                int ok = SWE_OK;
+                status.compare_exchange_strong(ok, rc);
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (int32_t t = 1; t < n_threads; ++t) pool.emplace_back(work);
+    } catch (const std::system_error &) {
+        // fewer threads than asked: the ones started and this one finish the parts
+    }
+    work();
+    for (auto &t : pool) t.join();
+    if (status.load() != SWE_OK) {
+        for (int32_t p = 0; p < P; ++p) {
+            delete out[p];
+            out[p] = nullptr;
+        }
+        return status.load();
+    }
     return SWE_OK;
 }
 

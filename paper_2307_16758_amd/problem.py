@@ -45,3 +45,21 @@ def prepare_scenario(sc, P: int = 1, p: int = 0, k: int = 0, nbr_global=None, pa
     ``manning``, ``inflow_q`` and ``outflow_stage`` attributes."""
     return prepare(sc.mesh.xy, sc.mesh.tri, sc.bc, sc.b, sc.manning, sc.inflow_q,
                    sc.outflow_stage, P=P, p=p, k=k, nbr_global=nbr_global, part=part)
+
+
+def prepare_parts(sc, P: int, k: int, nbr_global=None, part=None, threads: int = 0) -> list:
+    """All ``P`` parts of a scenario with ``k`` ghost layers, the ghost layers
+    and numbering of every part built on ``threads`` host threads; part q
+    equals ``prepare_scenario(sc, P, q, k)``."""
+    node_xy = np.ascontiguousarray(sc.mesh.xy, np.float64)
+    cell_nodes = np.ascontiguousarray(sc.mesh.tri, np.int32)
+    if nbr_global is None:
+        nbr_global = swe.swe_dual_graph(node_xy.shape[0], cell_nodes)
+    if part is None:
+        part = swe.swe_partition_bfs(nbr_global, P)
+    subs = swe.swe_subdomain_build_all(node_xy, cell_nodes, nbr_global, sc.bc, part, P, k, threads)
+    L_in = swe.swe_edge_length_sum(node_xy, cell_nodes, sc.bc, swe.BC_INFLOW)
+    return [Prepared(mesh=swe.mesh_from_subdomain(node_xy, cell_nodes, sc.b, sc.manning, sub,
+                                                  inflow_q=sc.inflow_q, inflow_length=L_in,
+                                                  outflow_stage=sc.outflow_stage),
+                     sub=sub, nbr_global=nbr_global, part=part) for sub in subs]

@@ -140,6 +140,9 @@ _sig("swe_morton_keys", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, C.POINTER(C.
 _sig("swe_subdomain_build", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, i32p,
                                       C.POINTER(C.c_int8), i32p, C.c_int32, C.c_int32,
                                       C.c_int32, C.POINTER(C.c_void_p)])
+_sig("swe_subdomain_build_all", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, i32p,
+                                          C.POINTER(C.c_int8), i32p, C.c_int32, C.c_int32,
+                                          C.c_int32, C.POINTER(C.c_void_p)])
 _sig("swe_subdomain_view_get", C.c_int, [C.c_void_p, C.POINTER(swe_subdomain_view)])
 _sig("swe_subdomain_free", None, [C.c_void_p])
 
@@ -152,7 +155,7 @@ EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error",
             "swe_trainer_create", "swe_trainer_destroy", "swe_trainer_loss_grad",
             "swe_trainer_step", "swe_trainer_get_params",
             "swe_dual_graph", "swe_partition_bfs", "swe_edge_length_sum", "swe_morton_keys", "swe_subdomain_build",
-            "swe_subdomain_view_get", "swe_subdomain_free"]
+            "swe_subdomain_build_all", "swe_subdomain_view_get", "swe_subdomain_free"]
 
 
 def lib():
@@ -231,6 +234,25 @@ def swe_subdomain_build(node_xy, cell_nodes, nbr, bc, part, P, p, k) -> SubDomai
     _check(_lib.swe_subdomain_build(x.shape[0], _f64(x), t.shape[0], _i32(t), _i32(nb),
                                     b.ctypes.data_as(C.POINTER(C.c_int8)), _i32(pa), P, p, k,
                                     C.byref(h)))
+    return _take_subdomain(h)
+
+
+def swe_subdomain_build_all(node_xy, cell_nodes, nbr, bc, part, P, k, threads=0) -> list:
+    """Every part of the partition, built on ``threads`` host threads."""
+    x = np.ascontiguousarray(node_xy, np.float64)
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    nb = np.ascontiguousarray(nbr, np.int32)
+    b = np.ascontiguousarray(bc, np.int8)
+    pa = np.ascontiguousarray(part, np.int32)
+    hs = (C.c_void_p * P)()
+    _check(_lib.swe_subdomain_build_all(x.shape[0], _f64(x), t.shape[0], _i32(t), _i32(nb),
+                                        b.ctypes.data_as(C.POINTER(C.c_int8)), _i32(pa), P, k,
+                                        int(threads), hs))
+    return [_take_subdomain(C.c_void_p(h)) for h in hs]
+
+
+def _take_subdomain(h) -> SubDomain:
+    """Copy a built sub-domain's arrays and free the library's object."""
     v = swe_subdomain_view()
     _check(_lib.swe_subdomain_view_get(h, C.byref(v)))
 

@@ -2,7 +2,8 @@
 greedy-BFS partition is a context of its own, all on one stream; each
 exchange packs the send lists on the device, moves them into the peers'
 receive blocks with one device gather (standing in for the communicator),
-and unpacks.  The CFL step is the minimum of the parts' local steps (the
+and unpacks.  The parts come from swe_subdomain_build_all (all parts on
+host threads).  The CFL step is the minimum of the parts' local steps (the
 reduction a multi-GPU run makes; a part with no wet owned cell imposes no
 bound), and it must equal the undecomposed run's step bit for bit; after
 the steps every owned cell equals the undecomposed run's cell bit for bit.
@@ -18,6 +19,7 @@ import numpy as np
 import pytest
 
 from gpu_util import SCHEME_KW, lib
+from paper_2307_16758_amd.problem import prepare_parts
 from swe_inputs import config2, config3
 
 pytestmark = pytest.mark.gpu
@@ -74,7 +76,7 @@ def _decomposed_vs_global(sc, name, P, k, per, rounds):
 
     pg = prepare_scenario(sc, nbr_global=nbr)
     g = solver(pg)
-    preps = [prepare_scenario(sc, P=P, p=q, k=k, nbr_global=nbr, part=part) for q in range(P)]
+    preps = prepare_parts(sc, P, k, nbr_global=nbr, part=part)     # on host threads
     assert sum(p.sub.n_owned for p in preps) == sc.n_cells
     subs = [solver(pr) for pr in preps]
     n_send, n_ghost, sbase, rbase, gather = _exchange_plan(preps)

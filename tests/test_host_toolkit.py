@@ -83,6 +83,57 @@ def test_river_part_bit_exact():
     _check_subdomains(sc, 32, (1, 2, 4), parts=[big, 0, 31])
 
 
+FIELDS = ("l2g", "layer", "owner", "nbr", "peers", "recv_off", "send_off", "send_idx")
+
+
+def test_all_parts_on_host_threads():
+    """swe_subdomain_build_all: every part equals the oracle's (config 1, 4
+    parts, k = 1, 2, 4) and the single-part build (a river of 130k cells,
+    32 parts, k = 4) for 1, 3 and 8 threads."""
+    sc = config1()
+    m = sc.mesh
+    nb = O.neighbors(m.n_nodes, m.tri)
+    part = O.partition(nb, 4)
+    for k in (1, 2, 4):
+        for threads in (1, 3, 8):
+            subs = swe.swe_subdomain_build_all(m.xy, m.tri, nb, sc.bc, part, 4, k, threads)
+            for p, b in enumerate(subs):
+                a = O.subdomain(m.xy, m.tri, nb, sc.bc, part, 4, p, k)
+                assert (a.n_owned, a.n_total) == (b.n_owned, b.n_total)
+                for f in FIELDS:
+                    np.testing.assert_array_equal(getattr(b, f), getattr(a, f), err_msg=f)
+    sc = river_dam_break(nx=570, ny=114, seed=3)
+    m = sc.mesh
+    nb = swe.swe_dual_graph(m.n_nodes, m.tri)
+    part = swe.swe_partition_bfs(nb, 32)
+    one = [swe.swe_subdomain_build(m.xy, m.tri, nb, sc.bc, part, 32, p, 4) for p in range(32)]
+    for threads in (1, 3, 8):
+        subs = swe.swe_subdomain_build_all(m.xy, m.tri, nb, sc.bc, part, 32, 4, threads)
+        for a, b in zip(one, subs):
+            assert (a.n_owned, a.n_total) == (b.n_owned, b.n_total)
+            for f in FIELDS:
+                np.testing.assert_array_equal(getattr(b, f), getattr(a, f), err_msg=f)
+
+
+def test_all_parts_error_leaves_no_part():
+    import ctypes as C
+    sc = config1()
+    m = sc.mesh
+    nb = swe.swe_dual_graph(m.n_nodes, m.tri)
+    part = swe.swe_partition_bfs(nb, 4)
+    part[77] = 9                                  # a part id outside [0, P)
+    hs = (C.c_void_p * 4)()
+    xy = np.ascontiguousarray(m.xy, np.float64)
+    tri = np.ascontiguousarray(m.tri, np.int32)
+    bc = np.ascontiguousarray(sc.bc, np.int8)
+    rc = swe.lib().swe_subdomain_build_all(xy.shape[0], xy.ctypes.data_as(swe.f64p), tri.shape[0],
+                                           tri.ctypes.data_as(swe.i32p), nb.ctypes.data_as(swe.i32p),
+                                           bc.ctypes.data_as(C.POINTER(C.c_int8)),
+                                           part.ctypes.data_as(swe.i32p), 4, 2, 3, hs)
+    assert rc == -1                               # SWE_ERR_ARG
+    assert all(h is None for h in hs)
+
+
 def test_inflow_length():
     sc = river_channel(Lx=2000.0, Ly=400.0, nx=60, ny=12, seed=5)
     L = swe.swe_edge_length_sum(sc.mesh.xy, sc.mesh.tri, sc.bc, swe.BC_INFLOW)
