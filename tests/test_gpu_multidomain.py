@@ -11,7 +11,8 @@ the steps every owned cell equals the undecomposed run's cell bit for bit.
 * the 13,000,560-cell river split into its 32 parts, k = 4, MUSCL-minmod-
   HLLC-RK2 (stencil radius 4: one step per exchange);
 * the 999,824-cell river split into 8 parts, k = 4, WAF (radius 2: two
-  steps per exchange) and first-order HLLC (radius 1: four steps).
+  steps per exchange) and first-order HLLC (radius 1: four steps), and
+  MUSCL-RK2 with the superbee, van Albada and learned limiters.
 """
 import time
 
@@ -57,17 +58,21 @@ def _combined_dt(local):
     return 0.0 if np.isinf(m) else m
 
 
-def _decomposed_vs_global(sc, name, P, k, per, rounds):
+def _decomposed_vs_global(sc, name, P, k, per, rounds, limiter=None, weights=None):
     import torch
     swe, prepare_scenario = lib()
     stream = torch.cuda.current_stream()
     kw = dict(SCHEME_KW[name], precision=0, stream=stream)
+    if limiter is not None:
+        kw["limiter"] = limiter
     nbr = swe.swe_dual_graph(sc.mesh.n_nodes, sc.mesh.tri)
     part = swe.swe_partition_bfs(nbr, P)
 
     def solver(pr):
         s = swe.Solver(**kw)
         s.mesh_upload(pr.mesh)
+        if weights is not None:
+            s.limiter_set_weights(weights)
         if sc.hydrograph is not None:
             s.set_bc_series(*sc.hydrograph)
         l2g = pr.sub.l2g
@@ -114,7 +119,8 @@ def _decomposed_vs_global(sc, name, P, k, per, rounds):
         assert s.health() == 0
     # the state has moved: the check compares evolved fields, not the input
     assert not np.array_equal(ref[0], sc.h)
-    print(f"{name}: {P} parts, {rounds} exchanges of {sum(n_send)} cells, "
+    label = name if limiter is None else f"MUSCL-RK2, limiter {limiter}"
+    print(f"{label}: {P} parts, {rounds} exchanges of {sum(n_send)} cells, "
           f"{1e3 * t_ex / rounds:.2f} ms per exchange (pack + gather + unpack, host-timed)")
     for s in subs:
         s.close()
@@ -129,3 +135,17 @@ def test_config3_all_32_parts_exchange_every_step():
 @pytest.mark.parametrize("name,per", [("waf", 2), ("hllc1", 4)])
 def test_config2_eight_parts(name, per):
     _decomposed_vs_global(config2(), name, P=8, k=4, per=per, rounds=3)
+
+
+@pytest.mark.parametrize("limiter", [1, 2, 3])
+def test_config2_eight_parts_other_limiters(limiter):
+    """Superbee, van Albada and the learned limiter (seeded random weights,
+    BF16 network ahead of every stage): the network's features come from a
+    cell and its neighbours, so a stage still reaches two layers and an
+    RK2 step four."""
+    from oracle import oracle as O
+    w = None
+    if limiter == 3:
+        w = np.random.default_rng(5).normal(0.0, 0.3, O.MLP_NPAR).astype(np.float32)
+    _decomposed_vs_global(config2(), "muscl_minmod_rk2", P=8, k=4, per=1, rounds=3,
+                          limiter=limiter, weights=w)
