@@ -167,12 +167,10 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
     // input the B operand (lane: half-edge col, inputs kq..kq+3) and the
     // bias the accumulator's initial value (lane: units kq..kq+3), so a
     // layer's accumulator (lane: units kq..kq+3 of half-edge col) is, after
-    // ReLU and BF16 rounding, the next layer's B operand as it stands.  The
-    // output layer has W3 in row 0 of A (the other rows zero): its result
-    // for half-edge col is row 0, i.e. element 0 in lanes 0..15.
+    // ReLU and BF16 rounding, the next layer's B operand as it stands.
     const int col = lane & 15, kq = (lane >> 4) * 4;
     const MlpDev *w = a.w;
-    s4v W1f[2], W2f[2][2], W3f[2];
+    s4v W1f[2], W2f[2][2], W3r[2];
     f4v b1v[2], b2v[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -183,29 +181,43 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         for (int j = 0; j < 4; ++j) {
             b1v[nt][j] = w->b1[nt * 16 + kq + j];
             b2v[nt][j] = w->b2[nt * 16 + kq + j];
-            W3f[nt][j] = col == 0 ? (short)bf16_bits_hw(w->W3[nt * 16 + kq + j]) : (short)0;
+            W3r[nt][j] = (short)bf16_bits_hw(w->W3[nt * 16 + kq + j]);
         }
     }
-    const f4v c3 = {kq == 0 ? w->b3 : 0.f, 0.f, 0.f, 0.f};
+    const s4v zero4 = {0, 0, 0, 0};
+    // b3 in element 0 of every lane: rows 0, 4, 8 and 12 of the accumulator
+    const f4v c3 = {w->b3, 0.f, 0.f, 0.f};
     wave_lds_sync();
-    for (int rt = 0; rt < 12; ++rt) {
-        // B: features kq..kq+3 of half-edge rt * 16 + col
-        const s4v xb = *(const s4v *)&X[wv][rt * 16 + col][kq];
-        const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, b1v[0], 0, 0, 0);
-        const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, b1v[1], 0, 0, 0);
-        const s4v h0 = relu_bf16x4(d0), h1 = relu_bf16x4(d1);
-        f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, b2v[0], 0, 0, 0);
-        e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][0], h1, e0, 0, 0, 0);
-        f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, b2v[1], 0, 0, 0);
-        e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][1], h1, e1, 0, 0, 0);
-        const s4v g0 = relu_bf16x4(e0), g1 = relu_bf16x4(e1);
-        f4v o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W3f[0], g0, c3, 0, 0, 0);
-        o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W3f[1], g1, o, 0, 0, 0);
-        if (lane < 16) {
-            const int row = rt * 16 + col;
-            const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-o[0])) : 0.5f;
-            if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
+    // Tiles in groups of four: the output layer of tile q holds W3 in row 4q
+    // of its A operand, so its 16 results are element 0 of lanes 16q..16q+15;
+    // one select per lane then gathers the four tiles, and the sigmoid and
+    // the store run once per group on all 64 lanes (half-edge rg * 64 + lane).
+    // Each tile keeps an accumulator of its own: a non-finite value in one
+    // tile cannot reach another's result.
+    for (int rg = 0; rg < 3; ++rg) {
+        f4v o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rt = rg * 4 + q;
+            // B: features kq..kq+3 of half-edge rt * 16 + col
+            const s4v xb = *(const s4v *)&X[wv][rt * 16 + col][kq];
+            const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, b1v[0], 0, 0, 0);
+            const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, b1v[1], 0, 0, 0);
+            const s4v h0 = relu_bf16x4(d0), h1 = relu_bf16x4(d1);
+            f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, b2v[0], 0, 0, 0);
+            e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][0], h1, e0, 0, 0, 0);
+            f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, b2v[1], 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][1], h1, e1, 0, 0, 0);
+            const s4v g0 = relu_bf16x4(e0), g1 = relu_bf16x4(e1);
+            const bool mine = col == 4 * q;
+            o[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mine ? W3r[0] : zero4, g0, c3, 0, 0, 0);
+            o[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mine ? W3r[1] : zero4, g1, o[q], 0, 0, 0);
         }
+        const int grp = lane >> 4;
+        const float z = grp == 0 ? o[0][0] : (grp == 1 ? o[1][0] : (grp == 2 ? o[2][0] : o[3][0]));
+        const int row = rg * 64 + lane;
+        const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-z)) : 0.5f;
+        if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
     }
 }
 
