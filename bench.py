@@ -84,11 +84,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name):
+def measured_traffic(workload_name, kernel="k_stage"):
     """HBM bytes per stage launch from the committed PMC summary of this
-    workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
-    None when it is absent or was taken on different kernel sources."""
-    f = os.path.join(ROOT, "profiles", f"k_stage_{workload_name}_traffic.md")
+    kernel and workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known
+    size), or None when it is absent or was taken on different kernel
+    sources."""
+    f = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_traffic.md")
     if not os.path.exists(f):
         return None
     vals = {}
@@ -286,10 +287,13 @@ def main():
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     # counters were taken on the plain-limiter stage kernel only
-                     "traffic": measured_traffic(args.workload)
-                     if (args.limiter == "minmod" and kw["scheme"] == 1 and not args.cell_kernel
-                         and not tuned) else None,
+                     # counters were taken on the plain-limiter MUSCL stage kernel and
+                     # on the tiled WAF kernel, in their default launch
+                     "traffic": (measured_traffic(args.workload)
+                                 if (args.limiter == "minmod" and kw["scheme"] == 1)
+                                 else measured_traffic(args.workload, "k_stage_tiled_waf")
+                                 if kw["scheme"] == 2 and kw["precision"] == 0 else None)
+                     if not args.cell_kernel and not tuned else None,
                      "kernel": ("autotuned stage kernel" if tuned else
                                 ("k_stage" if args.cell_kernel or (kw["scheme"] == 2 and kw["integrator"] == 1)
                                  else ("k_stage_tiled_waf" if kw["scheme"] == 2 else "k_stage_tiled"))
