@@ -105,7 +105,8 @@ typedef struct {
     double cfl;        /* default 0.45 */
     double eps;        /* wet/dry threshold [m], default 1e-6 */
     double dt_max;     /* cap on the CFL step (<= 0: none); step used when no cell is wet */
-    int block;         /* threads per block = cells per tile: 64, 128, 256 or 512 (0: 256);
+    int block;         /* threads per block = cells per tile: 64, 128, 256 or 512 (0: 256,
+                          64 for FP32 WAF with explicit Euler on the tiled kernel);
                           the one-thread-per-cell kernel, FP64 and WAF use at most 256
                           (FP64 WAF tiles at most 128) */
     int cell_kernel;   /* 1: one-thread-per-cell stage kernel for every scheme; 0: the

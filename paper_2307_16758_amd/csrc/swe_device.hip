@@ -1585,7 +1585,11 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     c->cfg = *cfg;
     c->dev = cfg->device;
     c->tsize = cfg->precision == SWE_F64 ? 8 : 4;
-    c->block = cfg->block ? cfg->block : 256;
+    // default tile: 256 cells, 64 for the FP32 tiled WAF kernel (its LDS
+    // per cell is larger, and smaller tiles keep more of them in flight)
+    const bool waf_tiled32 = cfg->scheme == SWE_WAF && cfg->integrator == SWE_EULER &&
+                             !cfg->cell_kernel && cfg->precision == SWE_F32;
+    c->block = cfg->block ? cfg->block : (waf_tiled32 ? 64 : 256);
     c->waves = cfg->waves;
     c->own_stream = cfg->stream == nullptr;
     if (!c->own_stream) c->stream = (hipStream_t)cfg->stream;
