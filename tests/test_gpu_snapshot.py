@@ -5,8 +5,9 @@ context's stream; the binding moves it to pinned host memory on a side
 stream while the following steps run.
 
 * snapshots taken between queued steps equal synchronous reads of a twin
-  context at the same step, bitwise (FP32, FP64, an ensemble context),
-  including the reuse of the two staging slots;
+  context at the same step, bitwise (FP32, FP64, an ensemble context, a
+  context on a torch stream with torch-allocated buffers), including the
+  reuse of the two staging slots;
 * buffers that are not device memory are refused and the context stays
   usable;
 * on the million-cell river the snapshots cost less than the synchronous
@@ -49,6 +50,31 @@ def test_snapshots_equal_synchronous_reads(prec):
             assert got[f].dtype == ref[f].dtype
             assert np.array_equal(got[f], ref[f]), (n, f)
     b.step(5)
+    for x, y in zip(a.read_state(), b.read_state()):
+        assert np.array_equal(x, y)
+
+
+def test_snapshot_on_a_borrowed_stream_with_torch_memory():
+    """A context on a torch stream, its buffers from torch's allocator: the
+    snapshot still equals a synchronous read at the same step, and torch work
+    queued on that stream after the snapshot does not disturb it."""
+    import torch
+    sc = _river()
+    st = torch.cuda.Stream()
+    a, _, _, pr = make_pair(sc, "muscl_minmod_rk2", precision=0, stream=st, allocator="torch")
+    b, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=0, prepared=pr)
+    with torch.cuda.stream(st):
+        a.step(15)
+        snap = a.snapshot()
+        junk = torch.full((1 << 22,), 3.0, device="cuda")   # torch work behind it on st
+        a.step(10)
+    b.step(15)
+    ref = b.read_state()
+    got = snap.wait()
+    for f in range(3):
+        assert np.array_equal(got[f], ref[f])
+    assert float(junk[0]) == 3.0
+    b.step(10)
     for x, y in zip(a.read_state(), b.read_state()):
         assert np.array_equal(x, y)
 
