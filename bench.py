@@ -1,19 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark: cell-updates/s of the MUSCL-HLLC-RK2 step on one MI355X.
 
-Workload (default ``config2``): the 10 km x 2 km meandering channel,
-1582 x 316 quads = 999,824 triangles, bumpy bed with dry banks, Manning n in
-[0.02, 0.05], 500 m^3/s inflow, fixed-stage outflow, FP32 state, minmod
-MUSCL + hydrostatic reconstruction + HLLC + Manning + SSP-RK2, CFL 0.45.
-One "step" is one full time step: both RK2 stages (reconstruction, fluxes,
-sources, friction, update) and the on-device CFL reduction for the next step;
-the state stays in HBM for the whole timed region.
+Workload (default ``config3_full``): the 40 km x 8 km meandering river,
+5702 x 1140 quads = 13,000,560 triangles, bumpy bed with dry banks and
+emerging islands, Manning n in [0.02, 0.05], a 2 m dam break at mid reach,
+500 m^3/s inflow, fixed-stage outflow, FP32 state, minmod MUSCL +
+hydrostatic reconstruction + HLLC + Manning + SSP-RK2, CFL 0.45.  One
+"step" is one full time step: both RK2 stages (reconstruction, fluxes,
+sources, friction, update) and the on-device CFL reduction for the next
+step; the state stays in HBM for the whole timed region.
 
-Prints one JSON line.  ``value`` = owned cells x steps / wall seconds.
-``roofline`` prices the stage kernel (the only kernel of the step) against
-8 TB/s with the per-cell algorithmic bytes of a stored-geometry design (212 B
-per MUSCL-RK2 cell-update); its launch time comes from HIP events recorded on
-the library's stream around the timed steps.
+Timing: W untimed warm-up steps, then the step graph is built (no capture
+inside a timed region), then five timed runs, each of K steps repeated
+until the run lasts at least 200 ms; ``value`` = owned cells x steps /
+seconds of the median run (host clock around the steps, stream synchronised
+on both sides).
+
+``roofline`` prices the step's dominant kernel against 8 TB/s with the
+compact algorithmic byte model of the step (state in and out, bed,
+Manning n, neighbour and node ids, node coordinates: 132 B per MUSCL-RK2
+cell-update in FP32, 60 B per first-order Euler update in FP32, 88 B per
+first-order FP64 update); its launch time comes from HIP events recorded on
+the library's stream around each timed run.  ``frac_stored_model`` gives the
+same time priced with the stored-geometry byte model (212 B per MUSCL-RK2
+update).  ``traffic`` is the HBM bytes per launch read from the committed
+rocprofv3 counter summary of the same kernel sources, or null.
 ``cpu_baseline`` times the serial FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
@@ -30,15 +41,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per cell-update of MUSCL-HLLC-RK2 in FP32 for a
-# design that stores the mesh geometry (the per-unit model of the hot-path
-# scope: 98 B for the first stage, 114 B for the second, 212 B per step; a
-# design that recomputes geometry from the nodes would move 132 B).  The
-# library's present layout moves more (336 B: see the measured traffic).
-BYTES_STAGE1 = 98
-BYTES_STAGE2 = 114
-BYTES_EULER_F64 = 132   # first-order HLLC, FP64, stored geometry
-BYTES_EULER_F32 = 102   # first-order WAF / HLLC, FP32, stored geometry
+
+
+def compact_bytes(precision, rk2):
+    """Algorithmic HBM bytes per cell-update, compact model (what one step
+    must move): per stage the state in (3 values) and out (3), bed and
+    Manning n (1 each), three neighbour ids and three node ids (4 B each)
+    and the node coordinates (about half a node per cell, 2 values); the
+    second RK2 stage also reads U^n (3 values).  FP32: 60 B per stage,
+    132 B per RK2 step.  The first-order FP64 figure leaves out Manning n
+    (88 B), as that workload has none."""
+    s = 8 if precision == 1 else 4
+    stage = 3 * s + s + s + 12 + 12 + s + 3 * s
+    if rk2:
+        return 2 * stage + 3 * s
+    return stage - (s if precision == 1 else 0)
+
+
+def stored_bytes(precision, rk2):
+    """The same with stored geometry instead of node coordinates (98 B +
+    114 B per FP32 RK2 step; 102 B FP32 / 132 B FP64 per Euler step)."""
+    if rk2:
+        return 212 * (2 if precision == 1 else 1)
+    return 132 if precision == 1 else 102
 
 
 MUSCL_RK2 = dict(precision=0, scheme=1, integrator=1, limiter=0)
@@ -84,7 +109,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name, kernel="k_stage"):
+def measured_traffic(workload_name, kernel):
     """HBM bytes per stage launch from the committed PMC summary of this
     kernel and workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known
     size), or None when it is absent or was taken on different kernel
@@ -105,9 +130,27 @@ def measured_traffic(workload_name, kernel="k_stage"):
         return None
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
 def cpu_baseline(sc, kw, seconds, mlp=None):
-    """Serial FP64 oracle on the same mesh: as many steps as fit in about
-    ``seconds`` (at least one), one core."""
+    """Serial FP64 oracle on the same mesh (its own neighbour search, in
+    the generator's numbering): as many steps as fit in about ``seconds``
+    (at least one), one thread."""
     from oracle import oracle as O
     M, _ = O.global_mesh(sc)
     p = O.scenario_params(sc, scheme=kw["scheme"], integrator=kw["integrator"],
@@ -122,17 +165,22 @@ def cpu_baseline(sc, kw, seconds, mlp=None):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    model, ncpu, avail = host_cpu()
     return dict(value=sc.n_cells * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=f"{sc.name}: {sc.n_cells} cells, first {steps} steps, serial FP64 "
-                       f"({el:.1f} s)")
+                       f"({el:.1f} s)",
+                host_cpu=model, nproc=ncpu, cores_available=avail)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1200)
-    ap.add_argument("--warmup", type=int, default=60)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--runs", type=int, default=5, help="timed runs (the median is reported)")
+    ap.add_argument("--min-run-ms", type=float, default=200.0,
+                    help="each timed run repeats the K steps until it lasts this long")
+    ap.add_argument("--workload", default="config3_full")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
@@ -220,88 +268,101 @@ def main():
         # snapshots: part of the warm-up, like the kernels' first launches
         for _ in range(3):
             s.snapshot().wait()
+    s.prepare()           # the step graph is captured here, outside every timed region
     s.sync()
-    if sendbuf is not None or args.snapshot_every > 0:
-        # the stage kernel alone (HIP events on the library stream), for the
-        # roofline; the state moves on, which the timed job below does not mind
-        s.step(args.steps)
+    kname, launches_per_step = s.step_kernel()
+    plain = sendbuf is None and args.snapshot_every <= 0
+
+    def one_run(nsteps):
+        """Host seconds of nsteps steps of the timed job, and the HIP-event
+        milliseconds of its kernels on the library stream (plain runs)."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if args.snapshot_every > 0:
+            snaps, done = [], 0
+            while done < nsteps:
+                m = min(args.snapshot_every, nsteps - done)
+                s.step(m)
+                done += m
+                snaps = snaps[-1:] + [s.snapshot()]   # older ones are complete (two slots)
+            s.sync()
+            for x in snaps:
+                x.wait()
+        elif sendbuf is None:
+            s.step(nsteps)
+            s.sync()
+        else:
+            for _ in range(nsteps):     # one step per exchange interval + on-device pack
+                s.step(1)
+                s.pack_ghosts(sendbuf)
+            s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, (s.last_step_ms() if plain else None)
+
+    # one untimed run of K steps sizes the timed runs: K steps repeated
+    # until a run lasts at least min_run_ms
+    w0, _ = one_run(args.steps)
+    reps = max(1, int(np.ceil(args.min_run_ms * 1e-3 / max(w0, 1e-9))))
+    per_run = args.steps * reps
+    runs = [one_run(per_run) for _ in range(args.runs)]
+    walls = sorted(r[0] for r in runs)
+    wall = walls[len(walls) // 2]
+    if plain:
+        ev = sorted(r[1] for r in runs)
+        gpu_ms = ev[len(ev) // 2]
+    else:
+        # the kernels alone (HIP events on the library stream) for the
+        # roofline; the state moves on, which the timed job does not mind
+        s.step(per_run)
         s.sync()
         gpu_ms = s.last_step_ms()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if args.snapshot_every > 0:
-        snaps, done = [], 0
-        while done < args.steps:
-            m = min(args.snapshot_every, args.steps - done)
-            s.step(m)
-            done += m
-            snaps = snaps[-1:] + [s.snapshot()]   # older ones are complete (two slots)
-        s.sync()
-        for x in snaps:
-            x.wait()
-    elif sendbuf is None:
-        s.step(args.steps)
-        s.sync()
-        gpu_ms = s.last_step_ms()       # HIP events around the timed steps, library stream
-    else:
-        for _ in range(args.steps):     # one step per exchange interval + on-device pack
-            s.step(1)
-            s.pack_ghosts(sendbuf)
-        s.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     health = s.health()
 
     rk2 = kw["integrator"] == 1
-    launches = args.steps * (2 if rk2 else 1)
+    prec = kw["precision"]
+    launches = per_run * launches_per_step
     avg_launch_s = gpu_ms * 1e-3 / launches
-    if rk2:
-        per_launch_bytes = (BYTES_STAGE1 + BYTES_STAGE2) / 2 * n_owned
-        if kw["precision"] == 1:
-            per_launch_bytes *= 2
-    else:
-        per_launch_bytes = (BYTES_EULER_F64 if kw["precision"] == 1 else BYTES_EULER_F32) * n_owned
+    per_launch_bytes = compact_bytes(prec, rk2) * n_owned / launches_per_step
     achieved = per_launch_bytes / avg_launch_s / 1e9
+    stored = stored_bytes(prec, rk2) * n_owned / launches_per_step / avg_launch_s / 1e9
+    traffic = None
+    if not args.cell_kernel and not tuned:
+        traffic = measured_traffic(args.workload, kname)
+    scheme_name = "MUSCL-HLLC" if rk2 else ("WAF" if kw["scheme"] == 2 else "HLLC")
+    model, ncpu, avail = host_cpu()
     out = {
-        "metric": "cell-updates/s ({}, {}, 1 GPU)".format(
-            "MUSCL-HLLC" if rk2 else ("WAF" if kw["scheme"] == 2 else "HLLC"),
-            "FP32" if kw["precision"] == 0 else "FP64"),
-        "value": n_owned * args.steps / wall,
+        "metric": "cell-updates/s ({}, {}, 1 GPU)".format(scheme_name, "FP32" if prec == 0 else "FP64"),
+        "value": n_owned * per_run / wall,
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * wall / per_run,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if kw["precision"] == 0 else "f64",
+        "dtype": "f32" if prec == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
-                               f"{'MUSCL-HLLC-RK2' if rk2 else ('WAF' if kw['scheme'] == 2 else 'HLLC') + '-Euler'}"
+                               f"{'MUSCL-HLLC-RK2' if rk2 else scheme_name + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
                                + (f", part of {P} with {k} ghost layers + pack" if P > 1 else "")
                                + (f", snapshot to host every {args.snapshot_every} steps"
                                   if args.snapshot_every > 0 else ""),
                    "cells": n_owned, "tuned_launch": tuned,
                    "parallelism": "single GPU" + (", one sub-domain" if P > 1 else ", single domain")},
+        "timing": {"runs": args.runs, "steps_per_run": per_run, "stat": "median",
+                   "run_ms": [1e3 * w for w in walls], "graph_prepared_before_timing": True},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     # counters were taken on the plain-limiter MUSCL stage kernel and
-                     # on the tiled WAF kernel, in their default launch
-                     "traffic": (measured_traffic(args.workload)
-                                 if (args.limiter == "minmod" and kw["scheme"] == 1)
-                                 else measured_traffic(args.workload, "k_stage_tiled_waf")
-                                 if kw["scheme"] == 2 and kw["precision"] == 0 else None)
-                     if not args.cell_kernel and not tuned else None,
-                     "kernel": ("autotuned stage kernel" if tuned else
-                                ("k_stage" if args.cell_kernel or (kw["scheme"] == 2 and kw["integrator"] == 1)
-                                 else ("k_stage_tiled_waf" if kw["scheme"] == 2 else "k_stage_tiled"))
-                                + (" + k_limiter_phi (per-launch time covers both)"
-                                   if args.limiter == "learned" else "")),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "launches_per_step": launches_per_step,
                      "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_launch": per_launch_bytes},
+                     "bytes_per_launch": per_launch_bytes,
+                     "byte_model": f"compact, {compact_bytes(prec, rk2)} B per cell-update",
+                     "frac_stored_model": stored / HBM_PEAK_GBS},
         "health_bits": health,
+        "host": {"cpu": model, "nproc": ncpu, "cores_available": avail},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc[0] if isinstance(sc, list) else sc, kw,

@@ -230,6 +230,20 @@ int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
  * (computed on the device from the owned cells, never copied to the host). */
 int swe_step(swe_ctx *ctx, int n_steps, double dt_fixed);
 
+/* Capture and instantiate the launch graph swe_step replays for runs of
+ * steps with this dt_fixed (dt_fixed <= 0: CFL mode), launching nothing, so
+ * that a following swe_step pays no capture on the host.  swe_step builds
+ * the same graph on first use when this was not called; a graph is rebuilt
+ * when dt_fixed or the launch shape changes.  SWE_ERR_STATE without a state
+ * (or without the network's weights for SWE_LEARNED). */
+int swe_prepare(swe_ctx *ctx, double dt_fixed);
+
+/* The kernel(s) one step launches under the context's configuration: *name
+ * points to a static string (kernel names joined by '+'), and
+ * *launches_per_step counts the launches of one step (e.g. 2 for the two
+ * stage launches of RK2).  For measurement tools. */
+int swe_step_kernel(const swe_ctx *ctx, const char **name, int *launches_per_step);
+
 int swe_sync(swe_ctx *ctx);                 /* wait + report health */
 int swe_time(swe_ctx *ctx, double *t);      /* simulated time (syncs) */
 /* CFL step of the current state over the owned cells (syncs): the step

@@ -1936,12 +1936,64 @@ int swe_snapshot(swe_ctx *c, void *h, void *hu, void *hv, void *done_event)
     return SWE_OK;
 }
 
-int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
+// Capture and instantiate the graph of kGraphSteps steps (the period of the
+// clock slots and of the state buffers, so one graph serves every aligned
+// run of steps) for this dt_fixed, unless it exists.  Nothing is launched.
+static int ensure_graph(swe_ctx *c, double dt_fixed)
 {
-    if (!c || n_steps < 0) return set_err(c, SWE_ERR_ARG, "bad argument");
+    if (c->graph && c->graph_dt == dt_fixed) return SWE_OK;
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    hipGraph_t gr = nullptr;
+    HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = SWE_OK;
+    for (int s = 0; s < kGraphSteps && rc == SWE_OK; ++s) rc = launch_step_any(c, s, dt_fixed);
+    hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (rc != SWE_OK) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+    if (e != hipSuccess) return set_err(c, SWE_ERR_DEVICE, "graph capture failed");
+    e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) { c->graph = nullptr; return set_err(c, SWE_ERR_DEVICE, "graph instantiation failed"); }
+    c->graph_dt = dt_fixed;
+    return SWE_OK;
+}
+
+static int step_ready(swe_ctx *c)
+{
     if (!c->has_state) return set_err(c, SWE_ERR_STATE, "no state");
     if (c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED && !c->has_mlp)
         return set_err(c, SWE_ERR_STATE, "learned limiter weights not set");
+    return SWE_OK;
+}
+
+int swe_step_kernel(const swe_ctx *c, const char **name, int *launches_per_step)
+{
+    if (!c || !name || !launches_per_step) return SWE_ERR_ARG;
+    const bool euler = c->cfg.integrator == SWE_EULER;
+    const bool cell_kernel = c->cfg.cell_kernel || (c->cfg.scheme == SWE_WAF && !euler);
+    const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
+    const int stages = euler ? 1 : 2;
+    if (cell_kernel) *name = "k_stage";
+    else if (c->cfg.scheme == SWE_WAF) *name = "k_stage_tiled_waf";
+    else *name = learned ? "k_stage_tiled+k_limiter_phi" : "k_stage_tiled";
+    *launches_per_step = stages * (learned ? 2 : 1);
+    return SWE_OK;
+}
+
+int swe_prepare(swe_ctx *c, double dt_fixed)
+{
+    if (!c) return SWE_ERR_ARG;
+    const int rc = step_ready(c);
+    if (rc != SWE_OK) return rc;
+    HIP_OK(c, hipSetDevice(c->dev));
+    if (!(dt_fixed > 0.0)) dt_fixed = 0.0;
+    return c->use_graphs ? ensure_graph(c, dt_fixed) : SWE_OK;
+}
+
+int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
+{
+    if (!c || n_steps < 0) return set_err(c, SWE_ERR_ARG, "bad argument");
+    const int ready = step_ready(c);
+    if (ready != SWE_OK) return ready;
     HIP_OK(c, hipSetDevice(c->dev));
     if (!(dt_fixed > 0.0)) dt_fixed = 0.0;
     HIP_OK(c, hipEventRecord(c->ev0, c->stream));
@@ -1949,20 +2001,8 @@ int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
     while (done < n_steps) {
         const bool aligned = (c->step_count % kGraphSteps) == 0;
         if (c->use_graphs && aligned && n_steps - done >= kGraphSteps) {
-            if (!c->graph || c->graph_dt != dt_fixed) {
-                if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
-                hipGraph_t gr = nullptr;
-                HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                int rc = SWE_OK;
-                for (int s = 0; s < kGraphSteps && rc == SWE_OK; ++s) rc = launch_step_any(c, s, dt_fixed);
-                hipError_t e = hipStreamEndCapture(c->stream, &gr);
-                if (rc != SWE_OK) { if (gr) (void)hipGraphDestroy(gr); return rc; }
-                if (e != hipSuccess) return set_err(c, SWE_ERR_DEVICE, "graph capture failed");
-                e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(gr);
-                if (e != hipSuccess) { c->graph = nullptr; return set_err(c, SWE_ERR_DEVICE, "graph instantiation failed"); }
-                c->graph_dt = dt_fixed;
-            }
+            const int rc = ensure_graph(c, dt_fixed);
+            if (rc != SWE_OK) return rc;
             HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
             c->step_count += kGraphSteps;
             done += kGraphSteps;

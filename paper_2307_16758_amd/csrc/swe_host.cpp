@@ -437,13 +437,13 @@ int prepare_geometry(const swe_mesh &M, int scenario, HostGeometry &g, std::stri
             if (M.cell_gid[c] < M.cell_gid[k]) word |= 1u << (6 + m);
             const double df = std::hypot(cx[k] - cx[c], cy[k] - cy[c]);
             const int32_t ua = nb[(m + 1) % 3], ub = nb[(m + 2) % 3];
+            if ((ua >= n) || (ub >= n)) { msg = "mesh: neighbour index out of range"; return SWE_ERR_MESH; }
             double ux = 0.0, uy = 0.0;
             bool up = true;
             if (ua >= 0 && ub >= 0) { ux = 0.5 * (cx[ua] + cx[ub]); uy = 0.5 * (cy[ua] + cy[ub]); }
             else if (ua >= 0) { ux = cx[ua]; uy = cy[ua]; }
             else if (ub >= 0) { ux = cx[ub]; uy = cy[ub]; }
             else up = false;
-            if ((ua >= n) || (ub >= n)) { msg = "mesh: neighbour index out of range"; return SWE_ERR_MESH; }
             gd[0] = up ? 1.0 / std::hypot(cx[c] - ux, cy[c] - uy) : 0.0;
             gd[1] = 1.0 / df;
             gd[2] = up ? 1.0 / std::hypot(cx[k] - ux, cy[k] - uy) : 0.0;

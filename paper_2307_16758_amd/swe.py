@@ -107,6 +107,8 @@ _sig("swe_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
                                 C.c_double])
 _sig("swe_read_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int])
 _sig("swe_step", C.c_int, [C.c_void_p, C.c_int, C.c_double])
+_sig("swe_prepare", C.c_int, [C.c_void_p, C.c_double])
+_sig("swe_step_kernel", C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_int)])
 _sig("swe_snapshot", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("swe_mesh_upload_batch", C.c_int, [C.c_void_p, C.c_int, C.POINTER(swe_mesh)])
 _sig("swe_set_bc_series_scenario", C.c_int, [C.c_void_p, C.c_int, C.c_int, f64p, f64p])
@@ -148,7 +150,7 @@ _sig("swe_subdomain_free", None, [C.c_void_p])
 
 EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error", "swe_strerror",
             "swe_mesh_upload", "swe_set_bc_series", "swe_set_state", "swe_read_state",
-            "swe_snapshot", "swe_step", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
+            "swe_snapshot", "swe_step", "swe_prepare", "swe_step_kernel", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
             "swe_batch_offsets", "swe_scenario_times", "swe_autotune", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
             "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
             "swe_limiter_set_weights", "swe_limiter_phi", "swe_limiter_pairs",
@@ -435,6 +437,27 @@ class Solver:
     def _chk(self, rc):
         _check(rc, self.ctx)
 
+    def _n_total(self):
+        return self.mesh.n_total if self.mesh is not None else 0
+
+    def _devbuf(self, t, n, what, dtype=None):
+        """Pointer of a device buffer the library will read or write ``n``
+        elements of: a contiguous CUDA tensor of the context's precision (or
+        ``dtype``) with at least ``n`` elements, else ValueError (a wrong
+        buffer would otherwise be overrun on the device)."""
+        import torch
+        want = dtype if dtype is not None else (torch.float64 if self.dtype == np.float64
+                                                else torch.float32)
+        if not (hasattr(t, "data_ptr") and getattr(t, "is_cuda", False)):
+            raise ValueError(f"{what}: a CUDA tensor is required")
+        if not t.is_contiguous():
+            raise ValueError(f"{what}: the tensor must be contiguous")
+        if t.dtype != want:
+            raise ValueError(f"{what}: dtype {t.dtype}, the context needs {want}")
+        if t.numel() < n:
+            raise ValueError(f"{what}: {t.numel()} elements, at least {n} needed")
+        return C.c_void_p(t.data_ptr())
+
     def mesh_upload(self, mesh: MeshArrays):
         s = mesh.c_struct()
         self._chk(_lib.swe_mesh_upload(self.ctx, C.byref(s)))
@@ -479,6 +502,8 @@ class Solver:
     def set_state(self, h, hu, hv, t=0.0):
         if hasattr(h, "data_ptr"):
             where = DEVICE
+            for a in (h, hu, hv):
+                self._devbuf(a, self._n_total(), "set_state")
         else:
             where = HOST
             h, hu, hv = (np.ascontiguousarray(a, self.dtype) for a in (h, hu, hv))
@@ -492,6 +517,12 @@ class Solver:
             where = HOST
         else:
             where = DEVICE if hasattr(out[0], "data_ptr") else HOST
+            for a in out:
+                if where == DEVICE:
+                    self._devbuf(a, self._n_total(), "read_state")
+                elif not (a.flags.c_contiguous and a.dtype == self.dtype and a.size >= self._n_total()):
+                    raise ValueError("read_state: contiguous host arrays of the context's dtype "
+                                     "with n_total elements are required")
         self._chk(_lib.swe_read_state(self.ctx, *(_ptr(a, where) for a in out), where))
         return out
 
@@ -535,6 +566,16 @@ class Solver:
     def step(self, n_steps, dt_fixed=0.0):
         self._chk(_lib.swe_step(self.ctx, int(n_steps), float(dt_fixed)))
 
+    def prepare(self, dt_fixed=0.0):
+        """Build the step graph for dt_fixed now (nothing runs)."""
+        self._chk(_lib.swe_prepare(self.ctx, float(dt_fixed)))
+
+    def step_kernel(self):
+        """(kernel name, launches per step) of the configured step."""
+        n, k = C.c_char_p(), C.c_int()
+        self._chk(_lib.swe_step_kernel(self.ctx, C.byref(n), C.byref(k)))
+        return n.value.decode(), k.value
+
     def sync(self):
         self._chk(_lib.swe_sync(self.ctx))
 
@@ -559,10 +600,14 @@ class Solver:
         return a.value, b.value
 
     def pack_ghosts(self, buf):
-        self._chk(_lib.swe_pack_ghosts(self.ctx, C.c_void_p(buf.data_ptr())))
+        """Send values of every peer into ``buf`` ([3][n_send] SoA)."""
+        n_send, _ = self.ghost_sizes()
+        self._chk(_lib.swe_pack_ghosts(self.ctx, self._devbuf(buf, 3 * n_send, "pack_ghosts")))
 
     def unpack_ghosts(self, buf):
-        self._chk(_lib.swe_unpack_ghosts(self.ctx, C.c_void_p(buf.data_ptr())))
+        """Ghost values of every peer from ``buf`` ([3][n_ghost] SoA)."""
+        _, n_ghost = self.ghost_sizes()
+        self._chk(_lib.swe_unpack_ghosts(self.ctx, self._devbuf(buf, 3 * n_ghost, "unpack_ghosts")))
 
     def last_step_ms(self):
         f = C.c_float()
@@ -577,13 +622,18 @@ class Solver:
 
     def limiter_phi(self, out):
         """phi of every half-edge into a float32 CUDA tensor of 3*n_total."""
-        self._chk(_lib.swe_limiter_phi(self.ctx, C.c_void_p(out.data_ptr())))
+        import torch
+        self._chk(_lib.swe_limiter_phi(self.ctx, self._devbuf(out, 3 * self._n_total(),
+                                                              "limiter_phi", torch.float32)))
 
     def limiter_pairs(self, fine: "Solver", children, out):
         """children: int32 CUDA tensor [4*n_total]; out: float32 CUDA tensor
         [3*n_total*32]."""
-        self._chk(_lib.swe_limiter_pairs(self.ctx, fine.ctx, C.c_void_p(children.data_ptr()),
-                                         C.c_void_p(out.data_ptr())))
+        import torch
+        n = self._n_total()
+        self._chk(_lib.swe_limiter_pairs(
+            self.ctx, fine.ctx, self._devbuf(children, 4 * n, "limiter_pairs children", torch.int32),
+            self._devbuf(out, 3 * n * 32, "limiter_pairs records", torch.float32)))
 
 
 class Trainer:

@@ -27,6 +27,6 @@ def test_traffic_is_dropped_when_kernels_change(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "ROOT", str(tmp_path))
     # sources are read from ROOT too: point them back at the real tree
     monkeypatch.setattr(b, "kernel_source_hash", lambda: h)
-    assert b.measured_traffic("demo") == 123.0
+    assert b.measured_traffic("demo", "k_stage") == 123.0
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 64)
-    assert b.measured_traffic("demo") is None
+    assert b.measured_traffic("demo", "k_stage") is None

@@ -13,7 +13,7 @@
 import numpy as np
 import pytest
 
-from gpu_util import make_pair, state_errors, lib
+from gpu_util import make_pair, state_errors, lib, oracle_side, assert_same_numbering
 from swe_inputs import config3, ensemble_scenarios
 
 pytestmark = pytest.mark.gpu
@@ -105,10 +105,9 @@ def test_config5_ensemble():
     i = int(order[0])
     x, p = scs[i], preps[i]
     l2g = p.sub.l2g
-    M = O.Mesh(x.mesh.xy, x.mesh.tri[l2g], p.sub.nbr, x.b[l2g], x.manning[l2g], gid=l2g,
-               n_owned=p.sub.n_owned)
+    M, osub = oracle_side(x)
+    assert_same_numbering(p.sub, osub)
     par = O.scenario_params(x, scheme=1, integrator=1, limiter=0)
-    par.inflow_len = p.mesh.inflow_length
     r = M.run(par, x.h[l2g], x.hu[l2g], x.hv[l2g], 10)
     sl = slice(off[i], off[i + 1])
     errs = state_errors([b[sl] for b in bst], r[:3], p.sub.n_owned)

@@ -89,36 +89,44 @@ def test_learned_limiter_steps(prec, tol):
 
 
 def fine_pair(sc, steps=100):
-    """Coarse and red-refined scenario, the fine one run on the GPU; returns
-    solvers, prepared meshes and the children map (coarse local -> fine local)."""
+    """Coarse and red-refined scenario, the fine one run by the oracle and
+    loaded into a solver; returns solvers, prepared meshes, the children map
+    (coarse local -> fine local) and the fine state on the host."""
     import torch
     swe, prepare_scenario = lib()
     fs = refine_scenario(sc)
-    fine, _, _, prf = make_pair(fs, "muscl_minmod_rk2", precision=0)
-    fine.step(steps)
+    fine, Mf, parf, prf = make_pair(fs, "muscl_minmod_rk2", precision=0)
+    # the fine solution comes from the oracle (rounded to the solver's FP32),
+    # so every input of the oracle calls below is the oracle's own
+    lf = prf.sub.l2g
+    rf = Mf.run(parf, fs.h[lf], fs.hu[lf], fs.hv[lf], steps)
+    fine_host = tuple(x.astype(np.float32) for x in rf[:3])
+    fine.set_state(*fine_host)
     coarse, Mc, parc, prc = make_pair(sc, "muscl_minmod_rk2", precision=0)
     g2l = np.empty(fs.n_cells, np.int64)
     g2l[prf.sub.l2g] = np.arange(prf.sub.n_total)
     gid = prc.sub.l2g
     ch = np.stack([g2l[4 * gid + k] for k in range(4)], 1).astype(np.int32)
     children = torch.from_numpy(ch.ravel().copy()).cuda()
-    return coarse, fine, prc, prf, ch, children, fs, Mc, parc
+    return coarse, fine, prc, prf, ch, children, fs, Mc, parc, fine_host
 
 
 def test_pairs_records():
     import torch
     sc = small_river()
-    coarse, fine, prc, prf, ch, children, fs, Mc, parc = fine_pair(sc)
+    coarse, fine, prc, prf, ch, children, fs, Mc, parc, fine_host = fine_pair(sc)
     n = prc.sub.n_total
     rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
     coarse.limiter_pairs(fine, children, rec)
     R = rec.cpu().numpy().reshape(n, 3, 32)
-    fh, fhu, fhv = fine.read_state()
+    fh, fhu, fhv = fine_host
     ch_h, ch_hu, ch_hv = fh[ch].astype(np.float64), fhu[ch].astype(np.float64), fhv[ch].astype(np.float64)
-    # restriction is the coarse state now
+    # the restriction (mean of the four children) is the coarse state now
     h, hu, hv = coarse.read_state()
     np.testing.assert_allclose(h, ch_h.mean(1), rtol=1e-6, atol=1e-6)
-    inp, _ = O.limiter_inputs(Mc, parc, h.astype(np.float64), hu.astype(np.float64), hv.astype(np.float64))
+    # the oracle's features of the same restriction, formed on the host from
+    # the oracle's fine state
+    inp, _ = O.limiter_inputs(Mc, parc, ch_h.mean(1), ch_hu.mean(1), ch_hv.mean(1))
     elig = inp[..., 23] == 1.0
     ok = R[..., 27] == 1.0
     assert ok.sum() > 1000 and np.all(elig[ok])

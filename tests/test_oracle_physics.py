@@ -19,7 +19,7 @@ from oracle import oracle as O
 from swe_inputs import (lake_at_rest, strip_riemann, dam_break_channel,
                         river_channel, grid_mesh)
 from swe_inputs.scenarios import _build, _flat_bed
-from swe_inputs.mesh import BC_WALL, BC_TRANSMISSIVE, BC_INFLOW
+from swe_inputs.mesh import BC_WALL, BC_TRANSMISSIVE, BC_INFLOW, BC_OUTFLOW
 
 SCHEMES = [
     ("hllc1", dict(scheme=O.HLLC1, integrator=O.EULER)),
@@ -300,3 +300,58 @@ def test_cfl_time_step():
     p.cfl_rule = 0
     p.dt_max = 1e-3
     assert M.dt(p, sc.h, sc.hu, sc.hv) == 1e-3
+
+
+@pytest.mark.parametrize("name,kw", SCHEMES)
+def test_outflow_lake_at_rest(name, kw):
+    """Fixed-stage outflow (reading of the configs' outlet): still water over
+    the bumpy river bed, with dry banks, whose level equals the outlet stage
+    stays at rest.  The outlet ghost depth is the stage less the bed of the
+    cell it faces, so every outlet edge meets an equal state; taking the
+    stage itself, or a dry ghost, would drain or fill the reach."""
+    sc = river_channel(Lx=1000.0, Ly=200.0, nx=60, ny=12, seed=23, inflow_q=0.0,
+                       stage=1.5, manning=0.03)
+    assert (sc.bc == -4).any() and (sc.h == 0).any()
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, **kw)
+    h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 1000)
+    assert fl == 0
+    wet = h > p.eps
+    assert np.abs(hu[wet] / h[wet]).max() <= 1e-12
+    assert np.abs(hv[wet] / h[wet]).max() <= 1e-12
+    assert np.abs(h - sc.h).max() <= 1e-12
+    assert t > 50.0
+
+
+@pytest.mark.parametrize("name,kw", SCHEMES[:2])
+def test_outflow_steady_uniform_stream(name, kw):
+    """A flat strip on a raised bed (b = 0.5 m), discharge Q = q W in at
+    x = 0, fixed stage eta_out = 2 m at x = L, no friction: the only steady
+    state is the uniform stream h = eta_out - b, hu = q, hv = 0 (the outlet
+    Riemann problem against a ghost of depth eta_out - b carrying the cell's
+    velocity then has equal sides, and its flux is the physical flux q of
+    the inflow).  The reach starts at rest and relaxes to it: a ghost depth
+    without the bed, or a ghost at rest, has another fixed point."""
+    W, L, b0, eta_out, q = 4.0, 60.0, 0.5, 2.0, 0.6
+    mesh = grid_mesh(L, W, 30, 2, seed=17)
+
+    def bed(x, y):
+        return np.full_like(x, b0)
+
+    def ic(x, y, b):
+        h = eta_out - b
+        return h, np.zeros_like(h), np.zeros_like(h)
+
+    sc = _build("outlet_strip", mesh, bed, ic, 0.0,
+                {0: BC_INFLOW, 1: BC_OUTFLOW, 2: BC_WALL, 3: BC_WALL},
+                inflow_q=q * W, outflow_stage=eta_out)
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, **kw)
+    assert p.inflow_len == pytest.approx(W, rel=1e-12)
+    # the slowest mode decays by about 10x every 400 s of simulated time
+    h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 70000)
+    assert fl == 0 and t > 2800.0
+    h_ex = eta_out - b0
+    assert np.abs(h - h_ex).max() <= 1e-9, np.abs(h - h_ex).max()
+    assert np.abs(hu - q).max() <= 1e-9, np.abs(hu - q).max()
+    assert np.abs(hv).max() <= 1e-9

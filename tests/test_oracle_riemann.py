@@ -185,3 +185,30 @@ def test_bf16_rounding():
     assert O.bf16(1.0 + 2 ** -8) == 1.0              # tie -> even
     assert O.bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
     assert O.bf16(-3.14159) == pytest.approx(-3.140625)
+
+
+def van_albada_ratio_form(a, b):
+    """Textbook van Albada slope limiter in ratio form: a * xi(r) with
+    r = b / a and xi(r) = r (1 + r) / (1 + r^2) for r > 0, else 0."""
+    if a == 0.0:
+        return 0.0
+    r = b / a
+    return a * r * (1.0 + r) / (1.0 + r * r) if r > 0.0 else 0.0
+
+
+def test_van_albada_values():
+    """Values that tell van Albada apart from the other symmetric limiters
+    bounded by the two slopes: at slopes (1, 3) van Albada gives 1.2, van
+    Leer's 2ab/(a+b) 1.5, the monotonized central limiter 2, minmod 1; for one
+    slope much larger than the other van Albada tends to the smaller one
+    (van Leer to twice it)."""
+    assert O.limiter(O.VANALBADA, 1.0, 3.0) == pytest.approx(1.2, rel=1e-15)
+    assert O.limiter(O.VANALBADA, 3.0, 1.0) == pytest.approx(1.2, rel=1e-15)
+    assert O.limiter(O.VANALBADA, -2.0, -6.0) == pytest.approx(-2.4, rel=1e-15)
+    assert O.limiter(O.VANALBADA, 2.0, 2.0) == pytest.approx(2.0, rel=1e-15)
+    assert O.limiter(O.VANALBADA, 1.0, 1e6) == pytest.approx(1.0, rel=2e-6)
+    assert O.limiter(O.VANALBADA, 1.0, -3.0) == 0.0
+    rng = np.random.default_rng(7)
+    for a, b in rng.normal(size=(2000, 2)) * np.exp(rng.normal(size=(2000, 2))):
+        assert O.limiter(O.VANALBADA, a, b) == pytest.approx(van_albada_ratio_form(a, b),
+                                                             rel=1e-13, abs=1e-300)
