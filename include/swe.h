@@ -317,6 +317,27 @@ int swe_trainer_loss_grad(swe_trainer *tr, const float *dev_rec, int32_t n_rec,
 int swe_trainer_step(swe_trainer *tr, const float *dev_rec, int32_t n_rec, const int32_t *dev_idx,
                      int32_t n, const float *wv, float lr, float *loss);
 int swe_trainer_get_params(swe_trainer *tr, float *host_params);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the loss and gradient of swe_trainer_loss_grad for parameters
+ * given as a device array dev_params[1569] (FP32, the trainer's layout),
+ * written to the caller's device buffer dev_grad_loss[1570] (gradient, then
+ * the loss), queued on `stream` (a hipStream_t; NULL is the null stream) of
+ * the current device, no host synchronisation.  It allocates nothing: the
+ * per-block partial sums live in a static device array of this library
+ * (512 blocks x 1570 floats, 3.2 MB per GPU, held until the process ends),
+ * whose size does not depend on n (the grid is capped at 512 blocks, each
+ * looping over chunks of 64 records), so no size is refused for want of
+ * workspace.  Bitwise equal to swe_trainer_loss_grad with the same
+ * parameters (same kernels, same grid, same reduction order).  Calls that
+ * overlap on one GPU share that array and race: order them on one stream.
+ * Errors: SWE_ERR_ARG for a null pointer or n, n_rec <= 0 (dev_idx entries
+ * outside [0, n_rec) count as absent records, as in the trainer);
+ * SWE_ERR_DEVICE when the array's address cannot be found or a launch
+ * fails. */
+int swe_trainer_loss_grad_static(const float *dev_params, const float *dev_rec, int32_t n_rec,
+                                 const int32_t *dev_idx, int32_t n, const float *wv,
+                                 float *dev_grad_loss, void *stream);
 
 /* ---- host mesh toolkit (Sec. 3.1 - 3.3), CPU only ---------------------- */
 /* Dual graph: cell across each local edge, -1 where none (global numbering).

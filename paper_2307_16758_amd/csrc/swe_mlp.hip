@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -483,12 +484,21 @@ int err(swe_ctx *c, int code, const std::string &m)
 
 }  // namespace
 
+constexpr int kTrainBlocks = 512;  // gradient partials: at most this many blocks
+constexpr int kMaxDevices = 64;    // devices whose static workspace address is kept
+
+// Per-block gradient partials of swe_trainer_loss_grad_static: a device array
+// of fixed size (3.2 MB), one copy per GPU, held until the process ends.  In
+// host code this name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (static_scratch_ptr).
+static __device__ __align__(256) float scratch[kTrainBlocks * (kMlpParams + 1)];
+
 struct swe_trainer {
     int dev = 0;
     hipStream_t stream = nullptr;
     float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *partial = nullptr;
     MlpDev *inf = nullptr;
-    int t = 0, nblocks = 512;
+    int t = 0, nblocks = kTrainBlocks;
     std::string err;
 };
 
@@ -628,18 +638,46 @@ void swe_trainer_destroy(swe_trainer *T)
     delete T;
 }
 
+// loss and gradient of n records into grad_loss[kMlpParams + 1]: per-block
+// partials in `partial` ([nblocks][kMlpParams + 1], every row written before
+// it is read, so nothing needs clearing), then a fixed-order reduction
+static int launch_grad(const float *params, const float *rec, int32_t n_rec, const int32_t *idx,
+                       int32_t n, const float *wv, float *partial, int nblocks, float *grad_loss,
+                       hipStream_t stream)
+{
+    TrainArgs a;
+    a.rec = rec; a.idx = idx; a.n = n; a.n_rec = n_rec; a.params = params; a.partial = partial;
+    for (int k = 0; k < 4; ++k) a.wv[k] = wv[k];
+    const int nchunks = (n + kChunk - 1) / kChunk;
+    const int G = nchunks < nblocks ? nchunks : nblocks;
+    hipLaunchKernelGGL(k_train_partial, dim3(G), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_train_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, stream,
+                       partial, G, n, grad_loss);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_ERR_DEVICE;
+}
+
 static int trainer_grad(swe_trainer *T, const float *rec, int32_t n_rec, const int32_t *idx,
                         int32_t n, const float *wv)
 {
-    TrainArgs a;
-    a.rec = rec; a.idx = idx; a.n = n; a.n_rec = n_rec; a.params = T->w; a.partial = T->partial;
-    for (int k = 0; k < 4; ++k) a.wv[k] = wv[k];
-    const int nchunks = (n + kChunk - 1) / kChunk;
-    const int G = nchunks < T->nblocks ? nchunks : T->nblocks;
-    hipLaunchKernelGGL(k_train_partial, dim3(G), dim3(256), 0, T->stream, a);
-    hipLaunchKernelGGL(k_train_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, T->stream,
-                       T->partial, G, n, T->grad);
-    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_ERR_DEVICE;
+    return launch_grad(T->w, rec, n_rec, idx, n, wv, T->partial, T->nblocks, T->grad, T->stream);
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy at its own address).
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMaxDevices];
+
+static int static_scratch_ptr(int dev, float **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return SWE_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SWE_ERR_DEVICE;
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SWE_OK;
 }
 
 int swe_trainer_loss_grad(swe_trainer *T, const float *rec, int32_t n_rec, const int32_t *idx,
@@ -675,6 +713,21 @@ int swe_trainer_step(swe_trainer *T, const float *rec, int32_t n_rec, const int3
             return SWE_ERR_DEVICE;
     }
     return SWE_OK;
+}
+
+int swe_trainer_loss_grad_static(const float *dev_params, const float *dev_rec, int32_t n_rec,
+                                 const int32_t *dev_idx, int32_t n, const float *wv,
+                                 float *dev_grad_loss, void *stream)
+{
+    if (!dev_params || !dev_rec || !dev_idx || !dev_grad_loss || !wv || n <= 0 || n_rec <= 0)
+        return SWE_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SWE_ERR_DEVICE;
+    float *partial = nullptr;
+    int rc = static_scratch_ptr(dev, &partial);
+    if (rc != SWE_OK) return rc;
+    return launch_grad(dev_params, dev_rec, n_rec, dev_idx, n, wv, partial, kTrainBlocks,
+                       dev_grad_loss, (hipStream_t)stream);
 }
 
 int swe_trainer_get_params(swe_trainer *T, float *host_params)

@@ -134,6 +134,9 @@ _sig("swe_trainer_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_v
 _sig("swe_trainer_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
                                    C.POINTER(C.c_float), C.c_float, C.POINTER(C.c_float)])
 _sig("swe_trainer_get_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float)])
+_sig("swe_trainer_loss_grad_static", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                               C.c_int32, C.POINTER(C.c_float), C.c_void_p,
+                                               C.c_void_p])
 _sig("swe_dual_graph", C.c_int, [C.c_int32, C.c_int32, i32p, i32p])
 _sig("swe_partition_bfs", C.c_int, [C.c_int32, i32p, C.c_int32, i32p])
 _sig("swe_edge_length_sum", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, C.POINTER(C.c_int8),
@@ -155,7 +158,7 @@ EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error",
             "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
             "swe_limiter_set_weights", "swe_limiter_phi", "swe_limiter_pairs",
             "swe_trainer_create", "swe_trainer_destroy", "swe_trainer_loss_grad",
-            "swe_trainer_step", "swe_trainer_get_params",
+            "swe_trainer_step", "swe_trainer_get_params", "swe_trainer_loss_grad_static",
             "swe_dual_graph", "swe_partition_bfs", "swe_edge_length_sum", "swe_morton_keys", "swe_subdomain_build",
             "swe_subdomain_build_all", "swe_subdomain_view_get", "swe_subdomain_free"]
 
@@ -634,6 +637,29 @@ class Solver:
         self._chk(_lib.swe_limiter_pairs(
             self.ctx, fine.ctx, self._devbuf(children, 4 * n, "limiter_pairs children", torch.int32),
             self._devbuf(out, 3 * n * 32, "limiter_pairs records", torch.float32)))
+
+
+def trainer_loss_grad_static(params, rec, idx, wv, out, stream=None):
+    """swe_trainer_loss_grad_static: loss and gradient for device parameters
+    without any allocation.  params: float32 CUDA tensor [1569]; rec: float32
+    CUDA tensor [n_rec*32]; idx: int32 CUDA tensor [n]; out: float32 CUDA
+    tensor [1570] (gradient, then the loss); queued on `stream` (a torch
+    stream; default: the current one), not synchronised."""
+    import torch
+    for t, n, dt, what in ((params, MLP_NPARAM, torch.float32, "params"),
+                           (rec, PAIR_RECORD, torch.float32, "rec"),
+                           (idx, 1, torch.int32, "idx"),
+                           (out, MLP_NPARAM + 1, torch.float32, "out")):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dt and t.numel() >= n):
+            raise SweError(-1, f"trainer_loss_grad_static: {what} must be a contiguous "
+                                        f"CUDA {dt} tensor of at least {n} elements")
+    w = np.ascontiguousarray(wv, np.float32)
+    assert w.shape == (4,)
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(_lib.swe_trainer_loss_grad_static(
+        C.c_void_p(params.data_ptr()), C.c_void_p(rec.data_ptr()), rec.numel() // PAIR_RECORD,
+        C.c_void_p(idx.data_ptr()), idx.numel(), w.ctypes.data_as(C.POINTER(C.c_float)),
+        C.c_void_p(out.data_ptr()), C.c_void_p(st)))
 
 
 class Trainer:
