@@ -372,6 +372,29 @@ int swe_subdomain_build_all(int32_t n_nodes, const double *node_xy, int32_t n_ce
                             const int32_t *cell_nodes, const int32_t *nbr, const int8_t *bc,
                             const int32_t *part, int32_t P, int32_t k, int32_t n_threads,
                             swe_subdomain **out);
+/* All P parts built the way Sec. 3.2 (Fig. `mainalg`) does it on
+ * distributed memory, one worker per part on n_threads host threads: each
+ * worker holds only its own cells (node ids, node coordinates, boundary
+ * tags) and matches their edges itself (no global dual graph); the workers
+ * share the bounding boxes of their nodes and centroids (all-gather), take
+ * as potential neighbours the parts whose closed node boxes meet theirs,
+ * build their k inner boundary layers (own cells within k edges of an edge
+ * not shared with another own cell), exchange those layers once with their
+ * potential neighbours, find ghost layer j as the received cells j edges
+ * from their own cells, tell each owner which cells they receive (its send
+ * lists) and number their cells as swe_subdomain_build does.  bc must tag
+ * every edge on the domain boundary (negative); an edge tagged 0 is
+ * interior, and one whose neighbour is not in the sub-domain becomes
+ * SWE_BC_HALO.  When no part lies within k layers of a part whose box does
+ * not meet its own, every out[p] equals swe_subdomain_build's; otherwise the
+ * ghosts owned by such a far part are missed (the limitation the paper
+ * states).  n_potential[P] (may be NULL) receives each part's number of
+ * potential neighbours.  Errors as swe_subdomain_build_all (SWE_ERR_MESH for
+ * an edge of more than two cells); on error every out[p] is NULL. */
+int swe_subdomain_build_layers(int32_t n_nodes, const double *node_xy, int32_t n_cells,
+                               const int32_t *cell_nodes, const int8_t *bc, const int32_t *part,
+                               int32_t P, int32_t k, int32_t n_threads, swe_subdomain **out,
+                               int32_t *n_potential);
 typedef struct {
     int32_t n_owned, n_total, n_peers, n_send;
     const int32_t *l2g;       /* [n_total] global id of each local cell */

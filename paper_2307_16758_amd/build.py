@@ -41,10 +41,12 @@ def run(cmd):
 def build(verbose: bool = True, out: str = LIB, flags=None) -> str:
     hip_flags = HIP_FLAGS if flags is None else flags
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    obj = os.path.join(HERE, "_build", "swe_host.o")
-    run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
-         os.path.join(CSRC, "swe_host.cpp"), "-o", obj])
-    objs = [obj]
+    objs = []
+    for src in ("swe_host.cpp", "swe_layers.cpp"):
+        obj = os.path.join(HERE, "_build", src.replace(".cpp", ".o"))
+        run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
+             os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
     for src in ("swe_device.hip", "swe_mlp.hip"):
         o = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
         run([HIPCC] + hip_flags + FILE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", o])

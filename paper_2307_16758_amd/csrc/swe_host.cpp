@@ -19,11 +19,6 @@
 
 #include "swe_internal.h"
 
-struct swe_subdomain {
-    int32_t n_owned = 0, n_total = 0, n_peers = 0, n_send = 0;
-    std::vector<int32_t> l2g, layer, owner, nbr, peers, recv_off, send_off, send_idx;
-};
-
 namespace {
 
 // Dual graph by sorting the 3n half-edges on their (min node, max node) key.

@@ -8,6 +8,13 @@
 
 #include "../../include/swe.h"
 
+// A sub-domain as the host toolkit builds it (swe_subdomain_view gives the
+// arrays): local numbering, ghost layers, neighbour table, peers and lists.
+struct swe_subdomain {
+    int32_t n_owned = 0, n_total = 0, n_peers = 0, n_send = 0;
+    std::vector<int32_t> l2g, layer, owner, nbr, peers, recv_off, send_off, send_idx;
+};
+
 namespace swe {
 
 // Packed per-cell word (4th int of the neighbour quad):

@@ -148,6 +148,9 @@ _sig("swe_subdomain_build", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, i32p,
 _sig("swe_subdomain_build_all", C.c_int, [C.c_int32, f64p, C.c_int32, i32p, i32p,
                                           C.POINTER(C.c_int8), i32p, C.c_int32, C.c_int32,
                                           C.c_int32, C.POINTER(C.c_void_p)])
+_sig("swe_subdomain_build_layers", C.c_int, [C.c_int32, f64p, C.c_int32, i32p,
+                                             C.POINTER(C.c_int8), i32p, C.c_int32, C.c_int32,
+                                             C.c_int32, C.POINTER(C.c_void_p), i32p])
 _sig("swe_subdomain_view_get", C.c_int, [C.c_void_p, C.POINTER(swe_subdomain_view)])
 _sig("swe_subdomain_free", None, [C.c_void_p])
 
@@ -160,7 +163,8 @@ EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error",
             "swe_trainer_create", "swe_trainer_destroy", "swe_trainer_loss_grad",
             "swe_trainer_step", "swe_trainer_get_params", "swe_trainer_loss_grad_static",
             "swe_dual_graph", "swe_partition_bfs", "swe_edge_length_sum", "swe_morton_keys", "swe_subdomain_build",
-            "swe_subdomain_build_all", "swe_subdomain_view_get", "swe_subdomain_free"]
+            "swe_subdomain_build_all", "swe_subdomain_build_layers", "swe_subdomain_view_get",
+            "swe_subdomain_free"]
 
 
 def lib():
@@ -254,6 +258,22 @@ def swe_subdomain_build_all(node_xy, cell_nodes, nbr, bc, part, P, k, threads=0)
                                         b.ctypes.data_as(C.POINTER(C.c_int8)), _i32(pa), P, k,
                                         int(threads), hs))
     return [_take_subdomain(C.c_void_p(h)) for h in hs]
+
+
+def swe_subdomain_build_layers(node_xy, cell_nodes, bc, part, P, k, threads=0):
+    """Every part built from its own cells and its potential neighbours'
+    inner boundary layers (no global dual graph); returns (parts, number of
+    potential neighbours of each part)."""
+    x = np.ascontiguousarray(node_xy, np.float64)
+    t = np.ascontiguousarray(cell_nodes, np.int32)
+    b = np.ascontiguousarray(bc, np.int8)
+    pa = np.ascontiguousarray(part, np.int32)
+    hs = (C.c_void_p * P)()
+    npot = np.zeros(P, np.int32)
+    _check(_lib.swe_subdomain_build_layers(x.shape[0], _f64(x), t.shape[0], _i32(t),
+                                           b.ctypes.data_as(C.POINTER(C.c_int8)), _i32(pa), P, k,
+                                           int(threads), hs, _i32(npot)))
+    return [_take_subdomain(C.c_void_p(h)) for h in hs], npot
 
 
 def _take_subdomain(h) -> SubDomain:
