@@ -195,6 +195,10 @@ def main():
     ap.add_argument("--snapshot-every", type=int, default=0, metavar="M",
                     help="take the state to pinned host memory every M steps (swe_snapshot, "
                          "copied on a side stream while the steps go on), inside the timed region")
+    ap.add_argument("--overlap", action="store_true",
+                    help="sub-domain workloads: each step with the high-overlap schedule "
+                         "(swe_step_overlap: send cells' tiles, pack on a side stream while the "
+                         "other tiles run) instead of a step followed by a pack")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for the HBM byte counters)")
@@ -291,6 +295,10 @@ def main():
         elif sendbuf is None:
             s.step(nsteps)
             s.sync()
+        elif args.overlap:
+            for _ in range(nsteps):     # one step per exchange interval, pack overlapped
+                s.step_overlap(sendbuf)
+            s.sync()
         else:
             for _ in range(nsteps):     # one step per exchange interval + on-device pack
                 s.step(1)
@@ -347,7 +355,8 @@ def main():
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
                                f"{'MUSCL-HLLC-RK2' if rk2 else scheme_name + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
-                               + (f", part of {P} with {k} ghost layers + pack" if P > 1 else "")
+                               + (f", part of {P} with {k} ghost layers + pack"
+                                  + (" (high-overlap steps)" if args.overlap else "") if P > 1 else "")
                                + (f", snapshot to host every {args.snapshot_every} steps"
                                   if args.snapshot_every > 0 else ""),
                    "cells": n_owned, "tuned_launch": tuned,

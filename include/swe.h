@@ -230,6 +230,22 @@ int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
  * (computed on the device from the owned cells, never copied to the host). */
 int swe_step(swe_ctx *ctx, int n_steps, double dt_fixed);
 
+/* One step with the high-overlap schedule of Sec. 6.4 (the send cells are
+ * computed first and their values leave while the interior is computed),
+ * as one GPU does it: the pack is fused into the step's last stage kernel.
+ * Each thread that computes a send cell's new state (the send cells are
+ * local cells [0, max(send_idx) + 1), numbered first, so their tiles are
+ * the first dispatched) also writes it to that cell's entries of
+ * dev_sendbuf ([3][n_send] as swe_pack_ghosts lays it out), while other
+ * tiles are still being computed; there is no pack launch.  The state,
+ * clock and buffer equal those of swe_step(ctx, 1, dt_fixed) followed by
+ * swe_pack_ghosts bitwise.  pack_done_event (a caller's hipEvent_t, may be
+ * NULL) is recorded on the context stream once the buffer is complete, so
+ * that a caller's exchange on another stream can wait for it.  Without send
+ * cells this is swe_step(ctx, 1, dt_fixed).  Asynchronous; not captured in
+ * the step graph.  SWE_ERR_ARG for a missing send buffer when n_send > 0. */
+int swe_step_overlap(swe_ctx *ctx, double dt_fixed, void *dev_sendbuf, void *pack_done_event);
+
 /* Capture and instantiate the launch graph swe_step replays for runs of
  * steps with this dt_fixed (dt_fixed <= 0: CFL mode), launching nothing, so
  * that a following swe_step pays no capture on the host.  swe_step builds

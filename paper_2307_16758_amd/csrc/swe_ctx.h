@@ -18,6 +18,7 @@ struct swe_ctx {
     std::string err;
     bool has_mesh = false, has_state = false, ran = false;
     int n_owned = 0, n_total = 0, n_scen = 1, n_send = 0, n_ghost = 0;
+    int send_prefix = 0;  // the send cells are local cells [0, send_prefix)
     size_t tsize = 4;
     // device buffers
     void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
@@ -31,6 +32,7 @@ struct swe_ctx {
     swe::ScenParams *scen = nullptr;
     double *ser_t = nullptr, *ser_q = nullptr, *t0 = nullptr;
     int *health = nullptr, *flag = nullptr, *send_idx = nullptr;
+    int *pk_off = nullptr, *pk_ent = nullptr;  // send entries per send cell (CSR)
     // host mirrors
     std::vector<swe::ScenParams> h_scen;
     std::vector<std::pair<std::vector<double>, std::vector<double>>> series;  // per scenario

@@ -341,7 +341,28 @@ template <typename T> struct StageArgs {
     int slot_cur, slot_next, slot_reset;
     int kind;  // 0: Euler step, 1: first RK2 stage, 2: second RK2 stage (+ average)
     int cfl_rule;
+    // fused pack of the high-overlap step (last stage only; pk_buf null
+    // otherwise): the new state of send cell c < pk_ncell goes to the send
+    // entries pk_ent[pk_off[c] .. pk_off[c+1]) of pk_buf ([3][pk_nsend])
+    const int *pk_off, *pk_ent;
+    T *pk_buf;
+    int pk_ncell, pk_nsend;
 };
+
+// Fused pack: the thread that has just computed send cell c's new state
+// writes it to every send entry of c (bitwise the stored state).
+template <typename T>
+__device__ __forceinline__ void pack_own(const StageArgs<T> &a, int c, T nh, T nu, T nv)
+{
+    if (a.pk_buf == nullptr || c >= a.pk_ncell) return;
+    const int e1 = a.pk_off[c + 1];
+    for (int e = a.pk_off[c]; e < e1; ++e) {
+        const int j = a.pk_ent[e];
+        a.pk_buf[j] = nh;
+        a.pk_buf[a.pk_nsend + j] = nu;
+        a.pk_buf[2 * a.pk_nsend + j] = nv;
+    }
+}
 
 // Boundary flux of Sec. 6.1 in the global frame.
 template <typename T, typename T4>
@@ -619,6 +640,7 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
         T4 out;
         out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
         a.Uout[c] = out;
+        pack_own(a, c, nh, nu, nv);
         if (flags) atomicOr(a.health, flags);
         cfl.scen = s;
         if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
@@ -909,6 +931,7 @@ k_stage_tiled(StageArgs<T> a)
             T4 out;
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
             stx(a.Uout, c, out);
+            pack_own(a, c, nh, nu, nv);
             if (flags) atomicOr(a.health, flags);
             cfl.scen = s;
             if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
@@ -1142,6 +1165,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
             T4 out;
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
             stx(a.Uout, c, out);
+            pack_own(a, c, nh, nu, nv);
             if (flags) atomicOr(a.health, flags);
             cfl.scen = s;
             if (((word >> kOwnedBit) & 1u) && nh > eps) {
@@ -1279,7 +1303,7 @@ void release_mesh(swe_ctx *c)
     dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam);
     dfree(c, c->U[0]); dfree(c, c->U[1]); dfree(c, c->U1); dfree(c, c->tmp3); dfree(c, c->bed);
     dfree_t(c, c->phi); dfree_t(c, c->clock); dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
-    dfree_t(c, c->t0); dfree_t(c, c->send_idx);
+    dfree_t(c, c->t0); dfree_t(c, c->send_idx); dfree_t(c, c->pk_off); dfree_t(c, c->pk_ent);
     c->has_mesh = c->has_state = false;
 }
 
@@ -1447,8 +1471,13 @@ template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm
     }
 }
 
+// Fused pack of the high-overlap step: the send buffer the last stage fills
+struct OverlapPlan {
+    void *sendbuf = nullptr;  // null: a plain step
+};
+
 template <typename T>
-int launch_step(swe_ctx *c, long long step, double dt_fixed)
+int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &ov = OverlapPlan())
 {
     using T4 = typename V4<T>::type;
     StageArgs<T> a{};
@@ -1493,6 +1522,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
     const dim3 blk(B);
     T4 *Ucur = (T4 *)c->U[step & 1];
     const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
+    T4 *Unext = (T4 *)c->U[(step + 1) & 1];
     if (c->cfg.integrator == SWE_RK2) {
         // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2
         if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
@@ -1500,12 +1530,18 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed)
         hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
         if (learned && launch_limiter_phi(c, c->U1) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 2; a.Uin = (T4 *)c->U1; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
-        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
     } else {
         if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 0; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
-        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
     }
+    if (ov.sendbuf && c->n_send > 0) {  // the last stage also fills the send buffer
+        a.pk_off = c->pk_off;
+        a.pk_ent = c->pk_ent;
+        a.pk_buf = (T *)ov.sendbuf;
+        a.pk_ncell = c->send_prefix;
+        a.pk_nsend = c->n_send;
+    }
+    hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
     HIP_OK(c, hipGetLastError());
     return SWE_OK;
 }
@@ -1702,6 +1738,8 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     c->n_owned = nm == 1 ? m->n_owned : c->n_total;
     c->n_scen = nm;
     c->n_send = n_send;
+    c->send_prefix = 0;
+    for (int i = 0; i < n_send; ++i) c->send_prefix = std::max(c->send_prefix, m->send_idx[i] + 1);
     c->n_ghost = n_ghost;
     c->scen_off = off;
     int rc = c->cfg.precision == SWE_F64 ? upload_geometry<double>(c, g) : upload_geometry<float>(c, g);
@@ -1731,6 +1769,17 @@ int upload_meshes(swe_ctx *c, const swe_mesh *ms, int nm)
     if (n_send > 0) {
         HIP_OK(c, dalloc(c, (void **)&c->send_idx, sizeof(int) * n_send));
         HIP_OK(c, hipMemcpy(c->send_idx, m->send_idx, sizeof(int) * n_send, hipMemcpyHostToDevice));
+        // send entries of each send cell (CSR over cells [0, send_prefix)),
+        // for the pack fused into the last stage of a high-overlap step
+        std::vector<int> off(c->send_prefix + 1, 0), ent(n_send);
+        for (int i = 0; i < n_send; ++i) off[m->send_idx[i] + 1]++;
+        for (int i = 0; i < c->send_prefix; ++i) off[i + 1] += off[i];
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int i = 0; i < n_send; ++i) ent[fill[m->send_idx[i]]++] = i;
+        HIP_OK(c, dalloc(c, (void **)&c->pk_off, sizeof(int) * (c->send_prefix + 1)));
+        HIP_OK(c, dalloc(c, (void **)&c->pk_ent, sizeof(int) * n_send));
+        HIP_OK(c, hipMemcpy(c->pk_off, off.data(), sizeof(int) * (c->send_prefix + 1), hipMemcpyHostToDevice));
+        HIP_OK(c, hipMemcpy(c->pk_ent, ent.data(), sizeof(int) * n_send, hipMemcpyHostToDevice));
     }
     c->h_scen.assign(nm, ScenParams{});
     c->series.assign(nm, {});
@@ -2013,6 +2062,27 @@ int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
             done += 1;
         }
     }
+    HIP_OK(c, hipEventRecord(c->ev1, c->stream));
+    c->ran = true;
+    return SWE_OK;
+}
+
+int swe_step_overlap(swe_ctx *c, double dt_fixed, void *dev_sendbuf, void *pack_done_event)
+{
+    if (!c) return SWE_ERR_ARG;
+    if (!dev_sendbuf && c->n_send > 0) return set_err(c, SWE_ERR_ARG, "null send buffer");
+    const int ready = step_ready(c);
+    if (ready != SWE_OK) return ready;
+    HIP_OK(c, hipSetDevice(c->dev));
+    if (!(dt_fixed > 0.0)) dt_fixed = 0.0;
+    HIP_OK(c, hipEventRecord(c->ev0, c->stream));
+    OverlapPlan ov;
+    ov.sendbuf = dev_sendbuf;
+    const int rc = c->cfg.precision == SWE_F64 ? launch_step<double>(c, c->step_count, dt_fixed, ov)
+                                               : launch_step<float>(c, c->step_count, dt_fixed, ov);
+    if (rc != SWE_OK) return rc;
+    if (pack_done_event) HIP_OK(c, hipEventRecord((hipEvent_t)pack_done_event, c->stream));
+    c->step_count += 1;
     HIP_OK(c, hipEventRecord(c->ev1, c->stream));
     c->ran = true;
     return SWE_OK;

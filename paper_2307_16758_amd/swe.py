@@ -108,6 +108,7 @@ _sig("swe_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
 _sig("swe_read_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int])
 _sig("swe_step", C.c_int, [C.c_void_p, C.c_int, C.c_double])
 _sig("swe_prepare", C.c_int, [C.c_void_p, C.c_double])
+_sig("swe_step_overlap", C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p])
 _sig("swe_step_kernel", C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_int)])
 _sig("swe_snapshot", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("swe_mesh_upload_batch", C.c_int, [C.c_void_p, C.c_int, C.POINTER(swe_mesh)])
@@ -156,7 +157,7 @@ _sig("swe_subdomain_free", None, [C.c_void_p])
 
 EXPORTED = ["swe_config_default", "swe_create", "swe_destroy", "swe_last_error", "swe_strerror",
             "swe_mesh_upload", "swe_set_bc_series", "swe_set_state", "swe_read_state",
-            "swe_snapshot", "swe_step", "swe_prepare", "swe_step_kernel", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
+            "swe_snapshot", "swe_step", "swe_step_overlap", "swe_prepare", "swe_step_kernel", "swe_mesh_upload_batch", "swe_set_bc_series_scenario",
             "swe_batch_offsets", "swe_scenario_times", "swe_autotune", "swe_sync", "swe_time", "swe_local_dt", "swe_health",
             "swe_pack_ghosts", "swe_unpack_ghosts", "swe_ghost_sizes", "swe_last_step_ms",
             "swe_limiter_set_weights", "swe_limiter_phi", "swe_limiter_pairs",
@@ -626,6 +627,23 @@ class Solver:
         """Send values of every peer into ``buf`` ([3][n_send] SoA)."""
         n_send, _ = self.ghost_sizes()
         self._chk(_lib.swe_pack_ghosts(self.ctx, self._devbuf(buf, 3 * n_send, "pack_ghosts")))
+
+    def step_overlap(self, buf, dt_fixed=0.0, event=None):
+        """One step with the high-overlap schedule: the last stage's threads
+        write the send cells' new values into ``buf`` ([3][n_send] SoA) as
+        they compute them (no pack launch); ``event`` (a torch.cuda.Event,
+        optional) is recorded once the buffer is complete."""
+        n_send, _ = self.ghost_sizes()
+        ev = None
+        if event is not None:
+            if hasattr(event, "cuda_event"):
+                if not event.cuda_event:   # torch creates its events lazily, at the first record
+                    event.record()
+                ev = C.c_void_p(event.cuda_event)
+            else:
+                ev = C.c_void_p(event)
+        self._chk(_lib.swe_step_overlap(self.ctx, float(dt_fixed),
+                                        self._devbuf(buf, 3 * n_send, "step_overlap"), ev))
 
     def unpack_ghosts(self, buf):
         """Ghost values of every peer from ``buf`` ([3][n_ghost] SoA)."""
