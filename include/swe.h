@@ -298,7 +298,7 @@ int swe_last_step_ms(swe_ctx *ctx, float *ms);
  * the classic limiter does (dry stencil cell, boundary edge).  Parameters
  * are 1569 floats: W1[32][14], b1[32], W2[32][32], b2[32], W3[32], b3. */
 #define SWE_MLP_NPARAM 1569
-#define SWE_PAIR_RECORD 32  /* floats per training record */
+#define SWE_PAIR_RECORD 40  /* floats per training record */
 /* Store the parameters (host, FP32) rounded to BF16 for the matrix-core
  * inference kernel. */
 int swe_limiter_set_weights(swe_ctx *ctx, const float *params);
@@ -310,18 +310,24 @@ int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
  * [4*n_total(coarse)]: fine local index of the four children of each coarse
  * cell (child k at parent node k, 3 the central one).  The coarse state is
  * set to the restriction (mean of the children) at t = 0, and dev_rec
- * [3*n_total(coarse)][32] receives per half-edge: features[14], cell values
+ * [3*n_total(coarse)][40] receives per half-edge: features[14], cell values
  * (h, eta, u_n, u_t)[4], central slopes[4], the target distance d = d_mid / 2,
  * target[4] = mean of the two children touching the edge (their mean
  * centroid lies halfway from the cell centroid to the edge midpoint), valid
- * flag, and the minmod interface values (h, eta, u_n, u_t)[4] at the edge
- * midpoint.  Children out of range give SWE_ERR_ARG. */
+ * flag, the minmod interface values (h, eta, u_n, u_t)[4] at the edge
+ * midpoint, backward slopes (q_c - q_upw)/d_up [4] and forward slopes
+ * (q_R - q_c)/d_fwd [4].  Children out of range give SWE_ERR_ARG. */
 int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_children, float *dev_rec);
 
 /* Trainer: FP32 master weights and Adam moments on one device.  The loss of
- * n records (indices dev_idx into dev_rec[n_rec][32]) is
- * (1/n) sum sum_v wv[v] (q_v + d phi s_v - t_v)^2 over v = h, eta, u_n, u_t
- * (d: the record's target distance). */
+ * n records (indices dev_idx into dev_rec[n_rec][40]) is
+ * (1/n) sum sum_v wv[v] (q_v + d clip(phi s_v, sb_v, sf_v) - t_v)^2 over
+ * v = h, eta, u_n, u_t (d: the record's target distance; clip: the TVD
+ * bound the solver applies to phi times the central slope, zero unless the
+ * backward and forward slopes sb, sf share a sign, else of the sign of sf
+ * and at most 2 min(|sb|, |sf|)), i.e. the misfit of the value the solver
+ * reconstructs.  The gradient is zero where the clip does not pass phi s
+ * through. */
 typedef struct swe_trainer swe_trainer;
 int swe_trainer_create(int device, const float *init_params, swe_trainer **out);
 void swe_trainer_destroy(swe_trainer *tr);

@@ -84,7 +84,7 @@ def lib():
         _lib.or_bf16.argtypes = [C.c_double]
         _lib.or_mlp_forward.argtypes = [dp, C.c_int, dp, C.c_int, dp]
         _lib.or_mlp_loss_grad.restype = C.c_double
-        _lib.or_mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp, dp, dp, dp, dp]
+        _lib.or_mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         _lib.or_limiter_inputs.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, dp, dp]
         _lib.od_neighbors.argtypes = [C.c_int, C.c_int, ip, ip]
         _lib.od_partition.argtypes = [C.c_int, ip, C.c_int, ip]
@@ -273,10 +273,11 @@ class Mesh:
 
 
 def limiter_inputs(mesh: "Mesh", params: Params, h, hu, hv):
-    """Per half-edge [n, 3, 24]: features[14], q[4], central slopes[4], d_mid,
-    eligible; and phi [n, 3] (0.5 where not eligible)."""
+    """Per half-edge [n, 3, 32]: features[14], q[4], central slopes[4], d_mid,
+    eligible, backward slopes[4], forward slopes[4]; and phi [n, 3] (0.5
+    where not eligible)."""
     h, hu, hv = (np.ascontiguousarray(a, np.float64) for a in (h, hu, hv))
-    out = np.empty((mesh.n, 3, 24))
+    out = np.empty((mesh.n, 3, 32))
     phi = np.empty((mesh.n, 3))
     p = params.c()
     lib().or_limiter_inputs(mesh.h, C.byref(p), _d(h), _d(hu), _d(hv), _d(out), _d(phi))
@@ -314,16 +315,17 @@ def mlp_forward(params, x, bf16_inputs=False):
     return phi
 
 
-def mlp_loss_grad(params, x, q, s, d, t, wv):
-    """Loss of the limiter training and its gradient (see swe_oracle.c)."""
+def mlp_loss_grad(params, x, q, s, sb, sf, d, t, wv):
+    """Loss of the limiter training and its gradient (see swe_oracle.c):
+    misfit of q + d clip(phi s, sb, sf) against the targets t."""
     w = np.ascontiguousarray(params, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, MLP_IN)
-    q, s, t = (np.ascontiguousarray(a, np.float64).reshape(-1, 4) for a in (q, s, t))
+    q, s, sb, sf, t = (np.ascontiguousarray(a, np.float64).reshape(-1, 4) for a in (q, s, sb, sf, t))
     d = np.ascontiguousarray(d, np.float64).ravel()
     wv = np.ascontiguousarray(wv, np.float64).ravel()
     g = np.zeros(MLP_NPAR)
-    loss = lib().or_mlp_loss_grad(_d(w), x.shape[0], _d(x), _d(q), _d(s), _d(d), _d(t),
-                                  _d(wv), _d(g))
+    loss = lib().or_mlp_loss_grad(_d(w), x.shape[0], _d(x), _d(q), _d(s), _d(sb), _d(sf), _d(d),
+                                  _d(t), _d(wv), _d(g))
     return loss, g
 
 

@@ -407,12 +407,17 @@ int or_mlp_forward(const double *params, int n, const double *x, int bf16, doubl
 }
 
 /* Loss of the limiter training: mean over n half-edges of
- *   sum_v wv[v] * (q_v + d * phi * s_v - t_v)^2,  v in {h, eta, hu, hv},
- * i.e. the squared misfit of the reconstructed interface value against the
- * refined-mesh target.  Returns the loss and accumulates dLoss/dparams. */
+ *   sum_v wv[v] * (q_v + d * clip(phi * s_v, sb_v, sf_v) - t_v)^2,
+ * v in {h, eta, u_n, u_t}, i.e. the squared misfit against the refined-mesh
+ * target of the value the solver reconstructs with this phi (the central
+ * slope s scaled by phi, kept in the TVD region of the backward and forward
+ * slopes sb, sf by tvd_clip), at distance d from the centroid.  The clip
+ * passes phi * s through where sb and sf agree in sign and |phi s| is below
+ * the bound; elsewhere the value does not depend on phi.  Returns the loss
+ * and accumulates dLoss/dparams. */
 double or_mlp_loss_grad(const double *params, int n, const double *x, const double *q,
-                        const double *s, const double *d, const double *t, const double *wv,
-                        double *grad)
+                        const double *s, const double *sb, const double *sf, const double *d,
+                        const double *t, const double *wv, double *grad)
 {
     mlp_view v = mlp_unpack(params);
     mlp_view gv = mlp_unpack(grad);
@@ -426,9 +431,11 @@ double or_mlp_loss_grad(const double *params, int n, const double *x, const doub
         double phi = mlp_forward(&v, xe, 0, a1, a2, &z);
         double dphi = 0.0;
         for (int k = 0; k < 4; ++k) {
-            double r = q[4 * e + k] + d[e] * phi * s[4 * e + k] - t[4 * e + k];
+            double sk = s[4 * e + k], b = sb[4 * e + k], f = sf[4 * e + k];
+            double r = q[4 * e + k] + d[e] * tvd_clip(phi * sk, b, f) - t[4 * e + k];
             loss += wv[k] * r * r;
-            dphi += 2.0 * wv[k] * r * d[e] * s[4 * e + k];
+            int passes = b * f > 0.0 && fabs(phi * sk) < 2.0 * fmin(fabs(b), fabs(f));
+            if (passes) dphi += 2.0 * wv[k] * r * d[e] * copysign(fabs(sk), f);
         }
         double dz = dphi * phi * (1.0 - phi) / n;
         gb3[0] += dz;
@@ -592,11 +599,12 @@ static iface reconstruct(const or_mesh *M, const or_params *P, const double *h, 
 }
 
 /* Inputs of the learned limiter for every half-edge (test access): for
- * half-edge e = 3c+m, out[24*e ..]: features[14], cell values (h, eta, u_n,
+ * half-edge e = 3c+m, out[32*e ..]: features[14], cell values (h, eta, u_n,
  * u_t)[4] in c's edge frame, central slopes (U_R - U_Lupw)/|x_R - x_Lupw|[4],
  * d_mid, eligibility (1: reconstructed to second order by MUSCL, 0: first
- * order); phi[e] = network output (bf16 layer inputs if P->mlp_bf16) or 0.5
- * where not eligible. */
+ * order), backward slopes (q_c - q_upw)/d_up [4] and forward slopes
+ * (q_R - q_c)/d_fwd [4] (zero where not eligible); phi[e] = network output
+ * (bf16 layer inputs if P->mlp_bf16) or 0.5 where not eligible. */
 int or_limiter_inputs(const or_mesh *M, const or_params *P, const double *h, const double *hu,
                       const double *hv, double *out, double *phi)
 {
@@ -604,8 +612,8 @@ int or_limiter_inputs(const or_mesh *M, const or_params *P, const double *h, con
     for (int c = 0; c < M->nc; ++c)
         for (int m = 0; m < 3; ++m) {
             int e = 3 * c + m;
-            double *o = out + 24 * (size_t)e;
-            for (int i = 0; i < 24; ++i) o[i] = 0.0;
+            double *o = out + 32 * (size_t)e;
+            for (int i = 0; i < 32; ++i) o[i] = 0.0;
             phi[e] = 0.5;
             double nx = M->enx[e], ny = M->eny[e];
             double qc[4];
@@ -643,7 +651,11 @@ int or_limiter_inputs(const or_mesh *M, const or_params *P, const double *h, con
             double qub[4] = {qu[0], qnu, qtu, bu};
             double qkb[4] = {h[k], hu[k] * nx + hv[k] * ny, -hu[k] * ny + hv[k] * nx, M->b[k]};
             halfedge_features(P->g, qcb, qub, qkb, du, df, dm, h[c], qc[2], qc[3], h[k], o);
-            for (int i = 0; i < 4; ++i) o[18 + i] = (qk[i] - qu[i]) / dc;
+            for (int i = 0; i < 4; ++i) {
+                o[18 + i] = (qk[i] - qu[i]) / dc;
+                o[24 + i] = (qc[i] - qu[i]) / du;
+                o[28 + i] = (qk[i] - qc[i]) / df;
+            }
             o[23] = 1.0;
             if (P->mlp) {
                 mlp_view v = mlp_unpack(P->mlp);

@@ -37,7 +37,7 @@ typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 namespace {
 
-constexpr int kRec = 32;  // floats per training record
+constexpr int kRec = 40;  // floats per training record
 
 // Inference weights: BF16 matrices (layer-1 K padded 14 -> 16 with zeros),
 // biases and the output layer as floats holding BF16-rounded values.
@@ -284,7 +284,7 @@ __global__ void k_pairs(PairArgs<T> a)
         for (int i = 0; i < kMlpIn; ++i) r[i] = f[i];
         T qc[4] = {Uc.x, Uc.x + Uc.w, T(0), T(0)};
         frame_vel(Uc, nx, ny, eps, qc[2], qc[3]);
-        T s[4] = {0, 0, 0, 0};
+        T s[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0}, sf[4] = {0, 0, 0, 0};
         if (ok) {
             const T4 &Uk = Un[m];
             T qk[4] = {Uk.x, Uk.x + Uk.w, T(0), T(0)};
@@ -300,10 +300,15 @@ __global__ void k_pairs(PairArgs<T> a)
                 qu[0] = Uo.x; qu[1] = Uo.x + Uo.w;
                 frame_vel(Uo, nx, ny, eps, qu[2], qu[3]);
             }
-            for (int i = 0; i < 4; ++i) s[i] = (qk[i] - qu[i]) * di.z;
+            for (int i = 0; i < 4; ++i) {
+                s[i] = (qk[i] - qu[i]) * di.z;
+                sb[i] = (qc[i] - qu[i]) * di.x;
+                sf[i] = (qk[i] - qc[i]) * di.y;
+            }
         }
         // target: mean of the two children touching edge m (at parent nodes m, m+1)
         const int ia = a.children[4 * c + m], ib = a.children[4 * c + (m + 1) % 3];
+        for (int i = 0; i < 4; ++i) { r[32 + i] = float(sb[i]); r[36 + i] = float(sf[i]); }
         if (ia < 0 || ia >= a.n_fine || ib < 0 || ib >= a.n_fine) { r[27] = 0.0f; continue; }
         const T4 fa = a.Uf[ia], fb = a.Uf[ib];
         T ua, va, ub, vb;
@@ -381,11 +386,20 @@ __global__ void __launch_bounds__(256) k_train_partial(TrainArgs a)
                 float z = b3[0];
                 for (int i = 0; i < kMlpH; ++i) z += W3[i] * a2[i];
                 const float phi = 1.0f / (1.0f + expf(-z));
+                // the value the solver reconstructs with this phi: the
+                // scaled central slope kept in the TVD region of the
+                // backward and forward slopes (no dependence on phi where
+                // the bound or the sign test decides)
                 float dphi = 0.f, loss = 0.f;
                 for (int k = 0; k < 4; ++k) {
-                    const float res = r[14 + k] + r[22] * phi * r[18 + k] - r[23 + k];
+                    const float sc = r[18 + k], sb = r[32 + k], sf = r[36 + k];
+                    const float sp = phi * sc;
+                    const bool pass = sb * sf > 0.f && fabsf(sp) < 2.f * fminf(fabsf(sb), fabsf(sf));
+                    const float cl = sb * sf > 0.f ? copysignf(fminf(fabsf(sp), 2.f * fminf(fabsf(sb), fabsf(sf))), sf)
+                                                   : 0.f;
+                    const float res = r[14 + k] + r[22] * cl - r[23 + k];
                     loss += a.wv[k] * res * res;
-                    dphi += 2.0f * a.wv[k] * res * r[22] * r[18 + k];
+                    if (pass) dphi += 2.0f * a.wv[k] * res * r[22] * copysignf(fabsf(sc), sf);
                 }
                 const float dz = dphi * phi * (1.0f - phi) / (float)a.n;
                 sdz[t] = dz;

@@ -76,7 +76,7 @@ def make_pair(sc, fine_sc):
 
 def records(pair: Pair, t_snap):
     """Run the fine solver to each snapshot time and collect the valid records
-    of the restricted coarse state (torch float32 [m, 32] on the device)."""
+    of the restricted coarse state (torch float32 [m, 40] on the device)."""
     import torch
     n = pair.coarse_prep.sub.n_total
     buf = torch.empty(3 * n * swe.PAIR_RECORD, dtype=torch.float32, device="cuda")

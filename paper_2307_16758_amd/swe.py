@@ -35,7 +35,7 @@ HOST, DEVICE = 0, 1
 BC_WALL, BC_TRANSMISSIVE, BC_INFLOW, BC_OUTFLOW, BC_HALO = -1, -2, -3, -4, -5
 HEALTH_NONFINITE, HEALTH_NEGDEPTH, HEALTH_CLIPPED = 1, 2, 4
 MLP_NPARAM = 1569
-PAIR_RECORD = 32
+PAIR_RECORD = 40
 
 
 class SweError(RuntimeError):
@@ -669,18 +669,18 @@ class Solver:
 
     def limiter_pairs(self, fine: "Solver", children, out):
         """children: int32 CUDA tensor [4*n_total]; out: float32 CUDA tensor
-        [3*n_total*32]."""
+        [3*n_total*40]."""
         import torch
         n = self._n_total()
         self._chk(_lib.swe_limiter_pairs(
             self.ctx, fine.ctx, self._devbuf(children, 4 * n, "limiter_pairs children", torch.int32),
-            self._devbuf(out, 3 * n * 32, "limiter_pairs records", torch.float32)))
+            self._devbuf(out, 3 * n * PAIR_RECORD, "limiter_pairs records", torch.float32)))
 
 
 def trainer_loss_grad_static(params, rec, idx, wv, out, stream=None):
     """swe_trainer_loss_grad_static: loss and gradient for device parameters
     without any allocation.  params: float32 CUDA tensor [1569]; rec: float32
-    CUDA tensor [n_rec*32]; idx: int32 CUDA tensor [n]; out: float32 CUDA
+    CUDA tensor [n_rec*40]; idx: int32 CUDA tensor [n]; out: float32 CUDA
     tensor [1570] (gradient, then the loss); queued on `stream` (a torch
     stream; default: the current one), not synchronised."""
     import torch

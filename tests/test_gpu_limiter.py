@@ -18,6 +18,10 @@ from swe_inputs import river_channel, refine_scenario
 pytestmark = pytest.mark.gpu
 
 
+def swe_mod():
+    return lib()[0]
+
+
 def bf16_round(a):
     a = np.asarray(a, np.float32)
     u = a.view(np.uint32).astype(np.uint64)
@@ -116,9 +120,9 @@ def test_pairs_records():
     sc = small_river()
     coarse, fine, prc, prf, ch, children, fs, Mc, parc, fine_host = fine_pair(sc)
     n = prc.sub.n_total
-    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    rec = torch.zeros(3 * n * swe_mod().PAIR_RECORD, dtype=torch.float32, device="cuda")
     coarse.limiter_pairs(fine, children, rec)
-    R = rec.cpu().numpy().reshape(n, 3, 32)
+    R = rec.cpu().numpy().reshape(n, 3, swe_mod().PAIR_RECORD)
     fh, fhu, fhv = fine_host
     ch_h, ch_hu, ch_hv = fh[ch].astype(np.float64), fhu[ch].astype(np.float64), fhv[ch].astype(np.float64)
     # the restriction (mean of the four children) is the coarse state now
@@ -133,6 +137,9 @@ def test_pairs_records():
     np.testing.assert_allclose(R[..., 14:18][ok], inp[..., 14:18][ok], rtol=1e-4, atol=1e-5)
     np.testing.assert_allclose(R[..., 18:22][ok], inp[..., 18:22][ok], rtol=1e-3, atol=1e-5)
     np.testing.assert_allclose(R[..., 22], 0.5 * inp[..., 22], rtol=1e-6)   # target distance
+    # backward and forward slopes (the training objective's TVD bound)
+    np.testing.assert_allclose(R[..., 32:36][ok], inp[..., 24:28][ok], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(R[..., 36:40][ok], inp[..., 28:32][ok], rtol=1e-3, atol=1e-5)
     assert np.abs(R[..., :14][ok] - inp[..., :14][ok]).max() < 1e-3
     # target depth: mean of the two children touching the edge
     for m in range(3):
@@ -146,9 +153,9 @@ def test_trainer_gradient_matches_oracle():
     sc = small_river()
     coarse, fine, prc, prf, ch, children, *_ = fine_pair(sc)
     n = prc.sub.n_total
-    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    rec = torch.zeros(3 * n * swe.PAIR_RECORD, dtype=torch.float32, device="cuda")
     coarse.limiter_pairs(fine, children, rec)
-    R = rec.cpu().numpy().reshape(-1, 32)
+    R = rec.cpu().numpy().reshape(-1, swe.PAIR_RECORD)
     valid = np.where(R[:, 27] == 1.0)[0].astype(np.int32)
     assert valid.size > 1000
     idx = torch.from_numpy(valid).cuda()
@@ -157,8 +164,8 @@ def test_trainer_gradient_matches_oracle():
     tr = swe.Trainer(w)
     loss, g = tr.loss_grad(rec, idx, wv)
     V = R[valid].astype(np.float64)
-    lo, go = O.mlp_loss_grad(w.astype(np.float64), V[:, :14], V[:, 14:18], V[:, 18:22], V[:, 22],
-                             V[:, 23:27], wv.astype(np.float64))
+    lo, go = O.mlp_loss_grad(w.astype(np.float64), V[:, :14], V[:, 14:18], V[:, 18:22],
+                             V[:, 32:36], V[:, 36:40], V[:, 22], V[:, 23:27], wv.astype(np.float64))
     assert loss == pytest.approx(lo, rel=1e-3)
     sizes = [32 * 14, 32, 32 * 32, 32, 32, 1]
     off = 0
@@ -178,9 +185,9 @@ def test_training_reduces_loss():
     sc = small_river()
     coarse, fine, prc, prf, ch, children, *_ = fine_pair(sc, steps=200)
     n = prc.sub.n_total
-    rec = torch.zeros(3 * n * 32, dtype=torch.float32, device="cuda")
+    rec = torch.zeros(3 * n * swe.PAIR_RECORD, dtype=torch.float32, device="cuda")
     coarse.limiter_pairs(fine, children, rec)
-    R = rec.view(-1, 32)
+    R = rec.view(-1, swe.PAIR_RECORD)
     valid = torch.nonzero(R[:, 27] == 1.0).flatten().to(torch.int32)
     tr = swe.Trainer(params(4, scale=0.1))
     wv = np.array([1.0, 1.0, 1.0, 1.0], np.float32)

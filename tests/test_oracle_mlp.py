@@ -15,30 +15,84 @@ def random_params(seed=0, scale=0.3):
 
 
 def random_batch(n=40, seed=1):
+    """Central slopes s with backward / forward slopes sb, sf around them:
+    same signs with bounds both above and below |phi s| (the clip passes or
+    binds), and a few of opposite signs (the clip gives zero)."""
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1.5, 1.5, (n, O.MLP_IN))
     q = rng.normal(size=(n, 4))
     s = rng.normal(size=(n, 4))
+    sb = s * rng.uniform(0.1, 1.5, (n, 4))
+    sf = s * rng.uniform(0.1, 1.5, (n, 4))
+    sf[::7] *= -1.0
     d = rng.uniform(0.5, 2.0, n)
     t = q + rng.normal(scale=0.3, size=(n, 4))
-    return x, q, s, d, t
+    return x, q, s, sb, sf, d, t
 
 
 def test_gradient_matches_finite_differences():
     w = random_params()
-    x, q, s, d, t = random_batch()
+    x, q, s, sb, sf, d, t = random_batch()
     wv = np.array([1.0, 0.5, 2.0, 0.7])
-    loss, g = O.mlp_loss_grad(w, x, q, s, d, t, wv)
+    loss, g = O.mlp_loss_grad(w, x, q, s, sb, sf, d, t, wv)
     h = 1e-6
     fd = np.empty_like(w)
     for i in range(w.size):
         wp, wm = w.copy(), w.copy()
         wp[i] += h
         wm[i] -= h
-        fd[i] = (O.mlp_loss_grad(wp, x, q, s, d, t, wv)[0] - O.mlp_loss_grad(wm, x, q, s, d, t, wv)[0]) / (2 * h)
+        fd[i] = (O.mlp_loss_grad(wp, x, q, s, sb, sf, d, t, wv)[0]
+                 - O.mlp_loss_grad(wm, x, q, s, sb, sf, d, t, wv)[0]) / (2 * h)
     scale = np.abs(fd).max()
     assert np.abs(g - fd).max() <= 1e-6 * scale
     assert loss > 0
+    # the clip both passes and binds in this batch: the gradient differs from
+    # the unclipped objective's (sb, sf far outside the bound)
+    big = 1e6 * np.sign(s)
+    _, g_free = O.mlp_loss_grad(w, x, q, s, big, big, d, t, wv)
+    assert np.abs(g - g_free).max() > 1e-3 * scale
+
+
+def test_training_loss_is_the_misfit_of_the_solver_reconstruction():
+    """With d = d_mid and zero targets, the training loss of a network whose
+    output is the constant phi0 equals the weighted mean square of the
+    interface values that the oracle's learned MUSCL step reconstructs with
+    phi0 (M.interfaces, an independent path through the solver): the
+    objective measures the clipped values the solver evaluates."""
+    sc = _river()
+    M, h, hu, hv = _flowing(sc)
+    w = np.zeros(O.MLP_NPAR)
+    w[-1] = np.log(0.7 / 0.3)            # output bias: phi = 0.7 everywhere
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED, mlp=w)
+    inp, phi = O.limiter_inputs(M, p, h, hu, hv)
+    rh, rb, run, rut, _ = M.interfaces(p, h, hu, hv)
+    got = np.stack([rh, rh + rb, run, rut], -1)
+    elig = (inp[..., 23] == 1.0) & (rh >= 0)
+    E = inp[elig]
+    assert E.shape[0] > 100 and np.allclose(phi[elig], 0.7)
+    wv = np.array([1.0, 0.5, 2.0, 0.7])
+    loss, _ = O.mlp_loss_grad(w, E[:, :14], E[:, 14:18], E[:, 18:22], E[:, 24:28], E[:, 28:32],
+                              E[:, 22], np.zeros((E.shape[0], 4)), wv)
+    direct = float(((got[elig] ** 2) * wv).sum(1).mean())
+    assert loss == pytest.approx(direct, rel=1e-12)
+
+
+def test_dumped_slopes_give_the_minmod_reconstruction():
+    """The backward and forward slopes of the limiter-input dump: q + d_mid
+    minmod(sb, sf) is the oracle's own minmod MUSCL reconstruction."""
+    sc = _river()
+    M, h, hu, hv = _flowing(sc)
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.MINMOD)
+    inp, _ = O.limiter_inputs(M, p, h, hu, hv)
+    mh, mb, mun, mut, _ = M.interfaces(p, h, hu, hv)
+    elig = (inp[..., 23] == 1.0) & (mh >= 0)
+    q, dm, sb, sf = inp[..., 14:18], inp[..., 22:23], inp[..., 24:28], inp[..., 28:32]
+    mm = np.where(sb * sf > 0, np.sign(sf) * np.minimum(np.abs(sb), np.abs(sf)), 0.0)
+    rec = q + dm * mm
+    scale = np.abs(q).max(axis=(0, 1)) + 1.0
+    assert (mm[elig] != 0).any()
+    for i, got in enumerate((mh, mh + mb, mun, mut)):
+        np.testing.assert_allclose(got[elig], rec[..., i][elig], rtol=0, atol=1e-12 * scale[i])
 
 
 def test_output_range_and_fixed_points():

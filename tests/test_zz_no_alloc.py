@@ -11,15 +11,17 @@ from gpu_util import lib
 pytestmark = pytest.mark.gpu
 
 
-def records(n_rec, seed):
+def records(n_rec, seed, width):
     rng = np.random.default_rng(seed)
-    R = np.zeros((n_rec, 32), np.float32)
+    R = np.zeros((n_rec, width), np.float32)
     R[:, :14] = rng.normal(0.0, 1.0, (n_rec, 14))          # features
     R[:, 14:18] = rng.uniform(0.5, 3.0, (n_rec, 4))        # cell values
     R[:, 18:22] = rng.normal(0.0, 0.05, (n_rec, 4))        # central slopes
     R[:, 22] = rng.uniform(1.0, 4.0, n_rec)                # target distance
     R[:, 23:27] = R[:, 14:18] + rng.normal(0.0, 0.05, (n_rec, 4))  # targets
     R[:, 27] = 1.0
+    R[:, 32:36] = R[:, 18:22] * rng.uniform(0.2, 1.5, (n_rec, 4))  # backward slopes
+    R[:, 36:40] = R[:, 18:22] * rng.uniform(0.2, 1.5, (n_rec, 4))  # forward slopes
     return R
 
 
@@ -35,7 +37,7 @@ def test_static_loss_grad_equals_trainer():
     # 40,000 records over 512 blocks, then 3,000 over 47 blocks; the index
     # lists pick a subset with repeats and one out-of-range entry (absent)
     for n_rec, n_idx, seed in ((40000, 50000, 1), (3000, 3000, 2)):
-        R = records(n_rec, seed)
+        R = records(n_rec, seed, swe.PAIR_RECORD)
         rec = torch.from_numpy(R.ravel()).cuda()
         idx_np = np.random.default_rng(seed + 10).integers(0, n_rec, n_idx).astype(np.int32)
         idx_np[5] = n_rec + 3
@@ -57,7 +59,7 @@ def test_static_loss_grad_rejects_bad_arguments():
     import torch
     swe, _ = lib()
     params = torch.zeros(swe.MLP_NPARAM, dtype=torch.float32, device="cuda")
-    rec = torch.zeros(32 * 10, dtype=torch.float32, device="cuda")
+    rec = torch.zeros(swe.PAIR_RECORD * 10, dtype=torch.float32, device="cuda")
     idx = torch.zeros(10, dtype=torch.int32, device="cuda")
     out = torch.zeros(swe.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
     wv = np.ones(4, np.float32)
