@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 2
+#define SWE_ABI_VERSION 3
 
 /* status codes */
 #define SWE_OK 0
@@ -130,9 +130,12 @@ typedef struct {
     void *(*alloc)(size_t bytes, void *user);
     void (*free)(void *ptr, void *user);
     void *alloc_user;
-    double waf_dry;    /* WAF: an edge with a hydrostatic interface depth below this [m]
-                          takes the first-order weights (A = 1, i.e. HLLC); keeps WAF's
-                          depths non-negative at wet/dry fronts.  Default 0.05 */
+    int waf_positivity; /* WAF: 1 (default) keeps depths non-negative at wet/dry fronts:
+                          an edge's mass flux out of a cell is at most 0.99 h R / (2 dt)
+                          (R the inscribed radius, i.e. the edge's share L / P of the
+                          cell's water per step); a WAF flux beyond it is blended
+                          towards the HLLC flux of the same states; 0: plain WAF */
+    int reserved1;
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).
@@ -295,7 +298,9 @@ int swe_last_step_ms(swe_ctx *ctx, float *ms);
  * becomes phi times the central slope (U_R - U_Lupw)/|x_R - x_Lupw| of
  * Sec. 6.2.3.  It falls back to the minmod slope when phi is outside [0,1]
  * or NaN or the reconstructed depth is negative, and to first order where
- * the classic limiter does (dry stencil cell, boundary edge).  Parameters
+ * the classic limiter does (dry stencil cell, boundary edge).  phi is
+ * evaluated once per time step, from the state the step starts from, and
+ * both RK2 stages use it.  Parameters
  * are 1569 floats: W1[32][14], b1[32], W2[32][32], b2[32], W3[32], b3. */
 #define SWE_MLP_NPARAM 1569
 #define SWE_PAIR_RECORD 40  /* floats per training record */
@@ -303,7 +308,8 @@ int swe_last_step_ms(swe_ctx *ctx, float *ms);
  * inference kernel. */
 int swe_limiter_set_weights(swe_ctx *ctx, const float *params);
 /* phi of every half-edge of the current state into dev_phi[3*n_total]
- * (0.5 where the half-edge is not reconstructed to second order). */
+ * (NaN where the half-edge is not reconstructed to second order: not
+ * evaluated). */
 int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
 /* Training records from a fine solution on the red refinement of the coarse
  * mesh (both contexts on one device, same precision).  dev_children

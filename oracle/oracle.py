@@ -47,7 +47,7 @@ class _Params(C.Structure):
                 ("inflow_len", C.c_double), ("outflow_stage", C.c_double),
                 ("n_series", C.c_int), ("pad", C.c_int),
                 ("series_t", C.POINTER(C.c_double)), ("series_q", C.POINTER(C.c_double)),
-                ("mlp", C.POINTER(C.c_double)), ("waf_dry", C.c_double)]
+                ("mlp", C.POINTER(C.c_double)), ("waf_pos", C.c_int), ("pad2", C.c_int)]
 
 
 class _Sub(C.Structure):
@@ -76,6 +76,8 @@ def lib():
         _lib.or_interfaces.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp,
                                        dp, dp, dp, dp, ip]
         _lib.or_riemann.argtypes = [C.POINTER(_Params), C.c_int, dp, dp, C.c_double, dp, dp]
+        _lib.or_waf_positivity.argtypes = [C.POINTER(_Params), dp, dp, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, dp]
         _lib.or_limiter.restype = C.c_double
         _lib.or_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
         _lib.or_superbee_A.restype = C.c_double
@@ -114,7 +116,7 @@ class Params:
     integrator: int = EULER
     limiter: int = MINMOD
     waf_limiter: int = WAF_SUPERBEE
-    waf_dry: float = 0.05
+    waf_pos: int = 1
     cfl_rule: int = 0
     mlp_bf16: int = 0
     inflow_q: float = 0.0
@@ -128,7 +130,7 @@ class Params:
         p = _Params(self.g, self.cfl, self.eps, self.dt_max, self.scheme, self.integrator,
                     self.limiter, self.waf_limiter, self.cfl_rule, self.mlp_bf16,
                     self.inflow_q, self.inflow_len, self.outflow_stage, 0, 0)
-        p.waf_dry = self.waf_dry
+        p.waf_pos = self.waf_pos
         self._keep = []
         if self.hydrograph is not None:
             t = np.ascontiguousarray(self.hydrograph[0], np.float64)
@@ -282,6 +284,16 @@ def limiter_inputs(mesh: "Mesh", params: Params, h, hu, hv):
     p = params.c()
     lib().or_limiter_inputs(mesh.h, C.byref(p), _d(h), _d(hu), _d(hv), _d(out), _d(phi))
     return out, phi
+
+
+def waf_positivity(params: Params, UL, UR, hL, RL, hR, RR, dt, F):
+    """The positivity blend of WAF applied to the flux F of one edge."""
+    UL, UR = (np.ascontiguousarray(a, np.float64) for a in (UL, UR))
+    out = np.array(F, np.float64, copy=True)
+    p = params.c()
+    lib().or_waf_positivity(C.byref(p), _d(UL), _d(UR), float(hL), float(RL), float(hR),
+                            float(RR), float(dt), _d(out))
+    return out
 
 
 def riemann(params: Params, scheme, UL, UR, dt_dx=0.0, ratio_in=None):

@@ -44,7 +44,8 @@ typedef struct {
     int n_series, pad;
     const double *series_t, *series_q;
     const double *mlp; /* MLP_NPAR weights, layout of mlp_unpack() */
-    double waf_dry;    /* WAF: an edge with a hydrostatic state shallower than this takes A = 1 */
+    int waf_pos;       /* WAF: 1 = mass flux kept within each donor cell's share (below) */
+    int pad2;
 } or_params;
 
 typedef struct {
@@ -59,6 +60,7 @@ typedef struct {
     double *rh, *rb, *run, *rut;  /* interface values per half-edge (own normal frame) */
     double *fx0, *fx1, *fx2;      /* half-edge flux incl. HR correction (global frame) */
     double *u0h, *u0u, *u0v, *u1h, *u1u, *u1v;
+    double *phi;                  /* learned limiter: phi of every half-edge for this step */
 } or_mesh;
 
 static double dmin(double a, double b) { return a < b ? a : b; }
@@ -117,7 +119,7 @@ void or_mesh_free(or_mesh *M)
                   (void **)&M->rh, (void **)&M->rb, (void **)&M->run, (void **)&M->rut,
                   (void **)&M->fx0, (void **)&M->fx1, (void **)&M->fx2, (void **)&M->u0h,
                   (void **)&M->u0u, (void **)&M->u0v, (void **)&M->u1h, (void **)&M->u1u,
-                  (void **)&M->u1v};
+                  (void **)&M->u1v, (void **)&M->phi};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(*p[i]);
     free(M);
 }
@@ -140,7 +142,7 @@ or_mesh *or_mesh_new(int nn, const double *xy, int nc, int n_owned, const int *t
                      &M->u1h, &M->u1u, &M->u1v};
     for (size_t i = 0; i < sizeof(pc) / sizeof(pc[0]); ++i) *pc[i] = malloc(sizeof(double) * nc);
     double **pe[] = {&M->enx, &M->eny, &M->elen, &M->emx, &M->emy, &M->rh, &M->rb, &M->run,
-                     &M->rut, &M->fx0, &M->fx1, &M->fx2};
+                     &M->rut, &M->fx0, &M->fx1, &M->fx2, &M->phi};
     for (size_t i = 0; i < sizeof(pe) / sizeof(pe[0]); ++i) *pe[i] = malloc(sizeof(double) * n3);
     if (geometry(M) != 0) { or_mesh_free(M); return NULL; }
     for (int c = 0; c < nc; ++c)
@@ -291,14 +293,11 @@ static double waf_A(int mode, double r, double c)
 
 static void flux_waf(double g, double eps, int mode, double dt_dx, const double UL[3],
                      const double UR[3], const waf_ratio_in *rh, const waf_ratio_in *rv,
-                     double waf_dry, double F[3])
+                     double F[3])
 {
     wave_fan W;
     wave_speeds(g, eps, UL, UR, &W);
     if (W.dry) { F[0] = F[1] = F[2] = 0.0; return; }
-    /* near a wet/dry front (either hydrostatic state shallower than
-     * waf_dry) the edge takes the first-order weights, A = 1 (HLLC) */
-    if (UL[0] < waf_dry || UR[0] < waf_dry) mode = OR_WAF_GODUNOV;
     double cL = W.SL * dt_dx, cR = W.SR * dt_dx, cs = W.Ss * dt_dx;
     double AL = waf_A(mode, waf_ratio(W.SL, rh), cL);
     double AR = waf_A(mode, waf_ratio(W.SR, rh), cR);
@@ -309,6 +308,35 @@ static void flux_waf(double g, double eps, int mode, double dt_dx, const double 
     for (int i = 0; i < 2; ++i) F[i] = wL * W.GL[i] + wLR * W.Fs[i] + wR * W.GR[i];
     double wLs = 0.5 * (1.0 + sgn(cs) * As), wRs = 0.5 * (1.0 - sgn(cs) * As);
     F[2] = (wLs * W.vL + wRs * W.vR) * F[0];
+}
+
+/* Positivity of WAF's depths (reading 10).  Over one step an edge may take
+ * from the cell it drains at most the share L / P of that cell's water (L
+ * the edge length, P the perimeter): a mass flux of at most
+ * h |Omega| / (P dt) = h R / (2 dt), R = 2 |Omega| / P the inscribed radius.
+ * Summed over its three edges no cell then loses more water than it holds;
+ * the bound is taken at 99% of that share so that rounding cannot take the
+ * last drop.  Where WAF's mass flux leaves these bounds (L's for a flux
+ * from L to R, R's for the reverse) the flux is blended towards the
+ * first-order HLLC flux of the same states, F = F_hllc + theta (F_waf -
+ * F_hllc), with the largest theta in [0, 1] that meets the bound, and the
+ * mass flux is set to the bound itself (exact).  If HLLC's own mass flux
+ * is beyond the bound the edge keeps whichever of the two is nearer. */
+static void waf_positivity(double g, double eps, const double UL[3], const double UR[3],
+                           double hL, double RL, double hR, double RR, double dt, double F[3])
+{
+    double hi = 0.99 * hL * RL / (2.0 * dt), lo = -(0.99 * hR * RR / (2.0 * dt));
+    if (F[0] <= hi && F[0] >= lo) return;
+    double bound = F[0] > hi ? hi : lo;
+    double Fh[3];
+    flux_hllc(g, eps, UL, UR, Fh);
+    double theta = (bound - Fh[0]) / (F[0] - Fh[0]);
+    if (!(theta > 0.0)) {                      /* HLLC is beyond the bound too */
+        for (int i = 0; i < 3; ++i) F[i] = Fh[i];
+    } else if (theta < 1.0) {
+        for (int i = 1; i < 3; ++i) F[i] = Fh[i] + theta * (F[i] - Fh[i]);
+        F[0] = bound;
+    }
 }
 
 /* ------------------------------------------------------------------------
@@ -568,15 +596,12 @@ static iface reconstruct(const or_mesh *M, const or_params *P, const double *h, 
     double dm = hypot(M->emx[3 * c + m] - M->cx[c], M->emy[3 * c + m] - M->cy[c]);
     double out[4];
     int learned_ok = 0;
+    (void)bu; (void)qnu; (void)qtu;
     if (P->limiter == OR_LEARNED && P->mlp) {
-        /* slope = phi * central slope (U_R - U_Lupw)/|x_R - x_Lupw| */
-        double qcb[4] = {h[c], hu[c] * nx + hv[c] * ny, -hu[c] * ny + hv[c] * nx, M->b[c]};
-        double qub[4] = {qu[0], qnu, qtu, bu};
-        double qkb[4] = {h[k], hu[k] * nx + hv[k] * ny, -hu[k] * ny + hv[k] * nx, M->b[k]};
-        double f[MLP_IN], a1[MLP_H], a2[MLP_H], z;
-        halfedge_features(P->g, qcb, qub, qkb, du, df, dm, h[c], qc[2], qc[3], h[k], f);
-        mlp_view v = mlp_unpack(P->mlp);
-        double phi = mlp_forward(&v, f, P->mlp_bf16, a1, a2, &z);
+        /* slope = phi * central slope (U_R - U_Lupw)/|x_R - x_Lupw|, with the
+         * phi of this half-edge evaluated once per step from the state the
+         * step starts from (step_phi) */
+        double phi = M->phi[3 * c + m];
         if (phi >= 0.0 && phi <= 1.0) { /* NaN fails both tests */
             double dc = hypot(M->cx[k] - xu, M->cy[k] - yu);
             for (int i = 0; i < 4; ++i) {
@@ -604,66 +629,85 @@ static iface reconstruct(const or_mesh *M, const or_params *P, const double *h, 
  * d_mid, eligibility (1: reconstructed to second order by MUSCL, 0: first
  * order), backward slopes (q_c - q_upw)/d_up [4] and forward slopes
  * (q_R - q_c)/d_fwd [4] (zero where not eligible); phi[e] = network output
- * (bf16 layer inputs if P->mlp_bf16) or 0.5 where not eligible. */
+ * (bf16 layer inputs if P->mlp_bf16), NaN where not eligible. */
+static void halfedge_inputs(const or_mesh *M, const or_params *P, const double *h,
+                            const double *hu, const double *hv, int c, int m, double o[32],
+                            double *phi)
+{
+    double eps = P->eps;
+    int e = 3 * c + m;
+    for (int i = 0; i < 32; ++i) o[i] = 0.0;
+    *phi = NAN;                               /* not evaluated */
+    double nx = M->enx[e], ny = M->eny[e];
+    double qc[4];
+    frame_state(M, h, hu, hv, eps, c, nx, ny, qc);
+    for (int i = 0; i < 4; ++i) o[14 + i] = qc[i];
+    double dm = hypot(M->emx[e] - M->cx[c], M->emy[e] - M->cy[c]);
+    o[22] = dm;
+    int k = M->nbr[e];
+    if (k < 0) return;
+    int a = M->nbr[3 * c + (m + 1) % 3], bb = M->nbr[3 * c + (m + 2) % 3];
+    if (h[c] <= eps || h[k] <= eps) return;
+    if ((a >= 0 && h[a] <= eps) || (bb >= 0 && h[bb] <= eps) || (a < 0 && bb < 0)) return;
+    double qk[4], qu[4], xu, yu, bu, qnu, qtu;
+    frame_state(M, h, hu, hv, eps, k, nx, ny, qk);
+    if (a >= 0 && bb >= 0) {
+        double qa[4], qb[4];
+        frame_state(M, h, hu, hv, eps, a, nx, ny, qa);
+        frame_state(M, h, hu, hv, eps, bb, nx, ny, qb);
+        for (int i = 0; i < 4; ++i) qu[i] = 0.5 * (qa[i] + qb[i]);
+        xu = 0.5 * (M->cx[a] + M->cx[bb]); yu = 0.5 * (M->cy[a] + M->cy[bb]);
+        bu = 0.5 * (M->b[a] + M->b[bb]);
+        qnu = 0.5 * ((hu[a] * nx + hv[a] * ny) + (hu[bb] * nx + hv[bb] * ny));
+        qtu = 0.5 * ((-hu[a] * ny + hv[a] * nx) + (-hu[bb] * ny + hv[bb] * nx));
+    } else {
+        int oo = a >= 0 ? a : bb;
+        frame_state(M, h, hu, hv, eps, oo, nx, ny, qu);
+        xu = M->cx[oo]; yu = M->cy[oo]; bu = M->b[oo];
+        qnu = hu[oo] * nx + hv[oo] * ny;
+        qtu = -hu[oo] * ny + hv[oo] * nx;
+    }
+    double du = hypot(M->cx[c] - xu, M->cy[c] - yu);
+    double df = hypot(M->cx[k] - M->cx[c], M->cy[k] - M->cy[c]);
+    double dc = hypot(M->cx[k] - xu, M->cy[k] - yu);
+    double qcb[4] = {h[c], hu[c] * nx + hv[c] * ny, -hu[c] * ny + hv[c] * nx, M->b[c]};
+    double qub[4] = {qu[0], qnu, qtu, bu};
+    double qkb[4] = {h[k], hu[k] * nx + hv[k] * ny, -hu[k] * ny + hv[k] * nx, M->b[k]};
+    halfedge_features(P->g, qcb, qub, qkb, du, df, dm, h[c], qc[2], qc[3], h[k], o);
+    for (int i = 0; i < 4; ++i) {
+        o[18 + i] = (qk[i] - qu[i]) / dc;
+        o[24 + i] = (qc[i] - qu[i]) / du;
+        o[28 + i] = (qk[i] - qc[i]) / df;
+    }
+    o[23] = 1.0;
+    if (P->mlp) {
+        mlp_view v = mlp_unpack(P->mlp);
+        double a1[MLP_H], a2[MLP_H], z;
+        *phi = mlp_forward(&v, o, P->mlp_bf16, a1, a2, &z);
+    }
+}
+
 int or_limiter_inputs(const or_mesh *M, const or_params *P, const double *h, const double *hu,
                       const double *hv, double *out, double *phi)
 {
-    double eps = P->eps;
     for (int c = 0; c < M->nc; ++c)
-        for (int m = 0; m < 3; ++m) {
-            int e = 3 * c + m;
-            double *o = out + 32 * (size_t)e;
-            for (int i = 0; i < 32; ++i) o[i] = 0.0;
-            phi[e] = 0.5;
-            double nx = M->enx[e], ny = M->eny[e];
-            double qc[4];
-            frame_state(M, h, hu, hv, eps, c, nx, ny, qc);
-            for (int i = 0; i < 4; ++i) o[14 + i] = qc[i];
-            double dm = hypot(M->emx[e] - M->cx[c], M->emy[e] - M->cy[c]);
-            o[22] = dm;
-            int k = M->nbr[e];
-            if (k < 0) continue;
-            int a = M->nbr[3 * c + (m + 1) % 3], bb = M->nbr[3 * c + (m + 2) % 3];
-            if (h[c] <= eps || h[k] <= eps) continue;
-            if ((a >= 0 && h[a] <= eps) || (bb >= 0 && h[bb] <= eps) || (a < 0 && bb < 0)) continue;
-            double qk[4], qu[4], xu, yu, bu, qnu, qtu;
-            frame_state(M, h, hu, hv, eps, k, nx, ny, qk);
-            if (a >= 0 && bb >= 0) {
-                double qa[4], qb[4];
-                frame_state(M, h, hu, hv, eps, a, nx, ny, qa);
-                frame_state(M, h, hu, hv, eps, bb, nx, ny, qb);
-                for (int i = 0; i < 4; ++i) qu[i] = 0.5 * (qa[i] + qb[i]);
-                xu = 0.5 * (M->cx[a] + M->cx[bb]); yu = 0.5 * (M->cy[a] + M->cy[bb]);
-                bu = 0.5 * (M->b[a] + M->b[bb]);
-                qnu = 0.5 * ((hu[a] * nx + hv[a] * ny) + (hu[bb] * nx + hv[bb] * ny));
-                qtu = 0.5 * ((-hu[a] * ny + hv[a] * nx) + (-hu[bb] * ny + hv[bb] * nx));
-            } else {
-                int oo = a >= 0 ? a : bb;
-                frame_state(M, h, hu, hv, eps, oo, nx, ny, qu);
-                xu = M->cx[oo]; yu = M->cy[oo]; bu = M->b[oo];
-                qnu = hu[oo] * nx + hv[oo] * ny;
-                qtu = -hu[oo] * ny + hv[oo] * nx;
-            }
-            double du = hypot(M->cx[c] - xu, M->cy[c] - yu);
-            double df = hypot(M->cx[k] - M->cx[c], M->cy[k] - M->cy[c]);
-            double dc = hypot(M->cx[k] - xu, M->cy[k] - yu);
-            double qcb[4] = {h[c], hu[c] * nx + hv[c] * ny, -hu[c] * ny + hv[c] * nx, M->b[c]};
-            double qub[4] = {qu[0], qnu, qtu, bu};
-            double qkb[4] = {h[k], hu[k] * nx + hv[k] * ny, -hu[k] * ny + hv[k] * nx, M->b[k]};
-            halfedge_features(P->g, qcb, qub, qkb, du, df, dm, h[c], qc[2], qc[3], h[k], o);
-            for (int i = 0; i < 4; ++i) {
-                o[18 + i] = (qk[i] - qu[i]) / dc;
-                o[24 + i] = (qc[i] - qu[i]) / du;
-                o[28 + i] = (qk[i] - qc[i]) / df;
-            }
-            o[23] = 1.0;
-            if (P->mlp) {
-                mlp_view v = mlp_unpack(P->mlp);
-                double a1[MLP_H], a2[MLP_H], z;
-                phi[e] = mlp_forward(&v, o, P->mlp_bf16, a1, a2, &z);
-            }
-        }
+        for (int m = 0; m < 3; ++m)
+            halfedge_inputs(M, P, h, hu, hv, c, m, out + 32 * (size_t)(3 * c + m), &phi[3 * c + m]);
     return 0;
+}
+
+/* The learned limiter's phi of every half-edge, evaluated once per time step
+ * from the state the step starts from and used by both RK2 stages.  Where
+ * that state does not reconstruct the half-edge to second order phi is not
+ * evaluated (NaN); a stage that does reconstruct it there (its own state
+ * decides) falls back to minmod, as for a network output outside [0, 1]. */
+static void step_phi(or_mesh *M, const or_params *P, const double *h, const double *hu,
+                     const double *hv)
+{
+    if (P->limiter != OR_LEARNED || !P->mlp || P->scheme != OR_MUSCL) return;
+    double o[32];
+    for (int c = 0; c < M->nc; ++c)
+        for (int m = 0; m < 3; ++m) halfedge_inputs(M, P, h, hu, hv, c, m, o, &M->phi[3 * c + m]);
 }
 
 /* rotation T_n of Sec. 6.1 and its inverse */
@@ -801,7 +845,9 @@ static void stage(or_mesh *M, const or_params *P, const double *h, const double 
                 else if (Ra >= 0) { rh_.qRu = et[2]; rv_.qRu = vt[2]; }
                 else if (Rb >= 0) { rh_.qRu = et[3]; rv_.qRu = vt[3]; }
                 double dx = hypot(M->cx[R] - M->cx[L], M->cy[R] - M->cy[L]);
-                flux_waf(g, eps, P->waf_limiter, dt / dx, UL, UR, &rh_, &rv_, P->waf_dry, F);
+                flux_waf(g, eps, P->waf_limiter, dt / dx, UL, UR, &rh_, &rv_, F);
+                if (P->waf_pos)
+                    waf_positivity(g, eps, UL, UR, h[L], M->inr[L], h[R], M->inr[R], dt, F);
             } else {
                 flux_hllc(g, eps, UL, UR, F);
             }
@@ -887,6 +933,7 @@ int or_run(or_mesh *M, const or_params *P, double *h, double *hu, double *hv, in
         double dt;
         if (dt_fixed > 0.0) dt = dt_fixed;
         else if (or_dt(M, P, h, hu, hv, &dt) != 0) return -1;
+        step_phi(M, P, h, hu, hv);
         if (P->integrator == OR_RK2) {
             stage(M, P, h, hu, hv, dt, *t, M->u0h, M->u0u, M->u0v, flags);
             stage(M, P, M->u0h, M->u0u, M->u0v, dt, *t + dt, M->u1h, M->u1u, M->u1v, flags);
@@ -914,12 +961,22 @@ int or_run(or_mesh *M, const or_params *P, double *h, double *hu, double *hv, in
 int or_interfaces(or_mesh *M, const or_params *P, const double *h, const double *hu,
                   const double *hv, double *rh, double *rb, double *run, double *rut, int *second)
 {
+    step_phi(M, P, h, hu, hv);
     for (int c = 0; c < M->nc; ++c)
         for (int m = 0; m < 3; ++m) {
             iface r = reconstruct(M, P, h, hu, hv, c, m);
             int e = 3 * c + m;
             rh[e] = r.h; rb[e] = r.b; run[e] = r.un; rut[e] = r.ut; second[e] = r.second;
         }
+    return 0;
+}
+
+/* The positivity blend of WAF on one edge (tests): F (in/out) is a flux in
+ * the normal frame for the states UL, UR. */
+int or_waf_positivity(const or_params *P, const double *UL, const double *UR, double hL,
+                      double RL, double hR, double RR, double dt, double *F)
+{
+    waf_positivity(P->g, P->eps, UL, UR, hL, RL, hR, RR, dt, F);
     return 0;
 }
 
@@ -935,7 +992,7 @@ int or_riemann(const or_params *P, int scheme, const double *UL, const double *U
             rv.qL = ratio_in[4]; rv.qR = ratio_in[5]; rv.qLu = ratio_in[6]; rv.qRu = ratio_in[7];
             rh.hasLu = rh.hasRu = rv.hasLu = rv.hasRu = 1;
         }
-        flux_waf(P->g, P->eps, P->waf_limiter, dt_dx, UL, UR, &rh, &rv, P->waf_dry, F);
+        flux_waf(P->g, P->eps, P->waf_limiter, dt_dx, UL, UR, &rh, &rv, F);
     } else {
         flux_hllc(P->g, P->eps, UL, UR, F);
     }

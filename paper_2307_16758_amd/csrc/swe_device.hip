@@ -336,7 +336,7 @@ template <typename T> struct StageArgs {
     const float *phi;
     int *health;
     T g, eps;
-    T waf_dry;  // WAF: first-order weights where a hydrostatic state is shallower
+    int waf_pos;  // WAF: mass fluxes kept within the donor cells' shares (waf_positivity)
     double cfl, dt_max, dt_fixed;
     int slot_cur, slot_next, slot_reset;
     int kind;  // 0: Euler step, 1: first RK2 stage, 2: second RK2 stage (+ average)
@@ -600,7 +600,12 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
                 const bool hk = waf_upwind(Uka, hka, Ukb, hkb, nLx, nLy, eps, ek, vk);
                 if (isL) { w.eLu = eo; w.vLu = vo; w.hasLu = ho; w.eRu = ek; w.vRu = vk; w.hasRu = hk; }
                 else { w.eLu = ek; w.vLu = vk; w.hasLu = hk; w.eRu = eo; w.vRu = vo; w.hasRu = ho; }
-                flux_waf<T, WAFM>(g, eps, fdiv(dt, dw.w), UL, UR, w, a.waf_dry, F);
+                flux_waf<T, WAFM>(g, eps, fdiv(dt, dw.w), UL, UR, w, F);
+                if (a.waf_pos) {
+                    const T Rc = cg.y, Rk = ((const T *)a.cell)[4 * (size_t)k + 1];
+                    waf_positivity(g, eps, UL, UR, isL ? Uc.x : Um.x, isL ? Rc : Rk, isL ? Um.x : Uc.x,
+                                   isL ? Rk : Rc, dt, F);
+                }
             } else {
                 flux_hllc(g, eps, UL, UR, F);
             }
@@ -1111,7 +1116,13 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 w.hasLu = isL ? oh : kh;
                 w.hasRu = isL ? kh : oh;
                 T F[3];
-                flux_waf<T, WAFM>(g, eps, fdiv(sDt[tl], a.he_dist[3 * tc + m].w), UL, UR, w, a.waf_dry, F);
+                const T dtt = sDt[tl];
+                flux_waf<T, WAFM>(g, eps, fdiv(dtt, a.he_dist[3 * tc + m].w), UL, UR, w, F);
+                if (a.waf_pos) {
+                    const T Ro = ((const T *)a.cell)[4 * (size_t)tc + 1];
+                    const T Rk = ((const T *)a.cell)[4 * (size_t)k + 1];
+                    waf_positivity(g, eps, UL, UR, Lv.x, isL ? Ro : Rk, Rv.x, isL ? Rk : Ro, dtt, F);
+                }
                 const T sg = isL ? T(1) : T(-1);
                 const T nLx = sg * nx, nLy = sg * ny;
                 const T G0 = F[0], G1 = F[1] * nLx - F[2] * nLy, G2 = F[1] * nLy + F[2] * nLx;
@@ -1499,7 +1510,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     a.health = c->health;
     a.g = T(c->cfg.g);
     a.eps = T(c->cfg.eps);
-    a.waf_dry = T(c->cfg.waf_dry);
+    a.waf_pos = c->cfg.waf_positivity;
     a.cfl = c->cfg.cfl;
     a.dt_max = c->cfg.dt_max;
     a.dt_fixed = dt_fixed;
@@ -1524,11 +1535,11 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
     T4 *Unext = (T4 *)c->U[(step + 1) & 1];
     if (c->cfg.integrator == SWE_RK2) {
-        // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2
+        // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2;
+        // the learned limiter's phi is evaluated once per step, from U^n
         if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 1; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U1;
         hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
-        if (learned && launch_limiter_phi(c, c->U1) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 2; a.Uin = (T4 *)c->U1; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
     } else {
         if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
@@ -1579,7 +1590,7 @@ void swe_config_default(swe_config *cfg)
     cfg->cfl = 0.45;
     cfg->eps = 1e-6;
     cfg->dt_max = 0.0;
-    cfg->waf_dry = 0.05;
+    cfg->waf_positivity = 1;
 }
 
 const char *swe_strerror(int code)
@@ -1609,7 +1620,7 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
-        !(cfg->eps >= 0) || !(cfg->waf_dry >= 0) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+        !(cfg->eps >= 0) || (cfg->waf_positivity != 0 && cfg->waf_positivity != 1) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
         (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7) || (!cfg->alloc != !cfg->free))
@@ -2024,7 +2035,7 @@ int swe_step_kernel(const swe_ctx *c, const char **name, int *launches_per_step)
     if (cell_kernel) *name = "k_stage";
     else if (c->cfg.scheme == SWE_WAF) *name = "k_stage_tiled_waf";
     else *name = learned ? "k_stage_tiled+k_limiter_phi" : "k_stage_tiled";
-    *launches_per_step = stages * (learned ? 2 : 1);
+    *launches_per_step = stages + (learned ? 1 : 0);
     return SWE_OK;
 }
 

@@ -267,20 +267,19 @@ template <typename T> struct WafIn {
     bool hasLu, hasRu;
 };
 
-// WAF flux; near a wet/dry front (a hydrostatic state shallower than
-// `shallow`) the first-order weights A = 1, i.e. HLLC.
+// WAF flux of Sec. 6.2.2 (TVD weights with the superbee A of eq.
+// eq:superbee, or the Godunov / unlimited weights).
 template <typename T, int MODE>
 __device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], const T UR[3],
-                                         const WafIn<T> &w, T shallow, T F[3])
+                                         const WafIn<T> &w, T F[3])
 {
     Fan<T> W;
     wave_fan(g, eps, UL, UR, W);
     if (W.dry) { F[0] = F[1] = F[2] = T(0); return; }
     const T cL = W.SL * dt_dx, cR = W.SR * dt_dx, cs = W.Ss * dt_dx;
-    const bool first = UL[0] < shallow || UR[0] < shallow;
-    const T AL = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.SL, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cL);
-    const T AR = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.SR, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cR);
-    const T As = first ? T(1) : waf_A<T, MODE>(waf_ratio(W.Ss, w.vL, w.vR, w.vLu, w.vRu, w.hasLu, w.hasRu), cs);
+    const T AL = waf_A<T, MODE>(waf_ratio(W.SL, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cL);
+    const T AR = waf_A<T, MODE>(waf_ratio(W.SR, w.eL, w.eR, w.eLu, w.eRu, w.hasLu, w.hasRu), cR);
+    const T As = waf_A<T, MODE>(waf_ratio(W.Ss, w.vL, w.vR, w.vLu, w.vRu, w.hasLu, w.hasRu), cs);
     const T wL = T(0.5) * (T(1) + sgn(cL) * AL);
     const T wLR = T(0.5) * (sgn(cR) * AR - sgn(cL) * AL);
     const T wR = T(0.5) * (T(1) - sgn(cR) * AR);
@@ -288,6 +287,38 @@ __device__ __forceinline__ void flux_waf(T g, T eps, T dt_dx, const T UL[3], con
     for (int i = 0; i < 2; ++i) F[i] = wL * W.GL[i] + wLR * W.Fs[i] + wR * W.GR[i];
     const T wLs = T(0.5) * (T(1) + sgn(cs) * As), wRs = T(0.5) * (T(1) - sgn(cs) * As);
     F[2] = (wLs * W.vL + wRs * W.vR) * F[0];
+}
+
+// Positivity of WAF's depths.  Over one step an edge may take from the
+// cell it drains at most the share L / P of that cell's water (L the edge
+// length, P the perimeter): a mass flux of at most h |Omega| / (P dt) =
+// h R / (2 dt), R = 2 |Omega| / P the inscribed radius, so that summed over
+// its three edges no cell loses more than it holds; the bound is taken at
+// 99% of the share so that rounding cannot take the last drop.  A WAF flux
+// whose mass component leaves the bounds of L (flux from L to R) or R (the
+// reverse) is blended towards the first-order HLLC flux of the same states,
+// F = F_hllc + theta (F_waf - F_hllc), with the largest theta in [0, 1]
+// meeting the bound, and its mass component is set to the bound; when HLLC
+// is itself beyond the bound the edge takes HLLC.  hL, hR: the cells'
+// depths; RL, RR: their inscribed radii (canonical orientation, so both
+// sides of an edge compute the same bits).
+template <typename T>
+__device__ __forceinline__ void waf_positivity(T g, T eps, const T UL[3], const T UR[3], T hL, T RL,
+                                               T hR, T RR, T dt, T F[3])
+{
+    const T hi = fdiv(T(0.99) * hL * RL, T(2) * dt), lo = -fdiv(T(0.99) * hR * RR, T(2) * dt);
+    if (F[0] <= hi && F[0] >= lo) return;
+    const T bound = F[0] > hi ? hi : lo;
+    T Fh[3];
+    flux_hllc(g, eps, UL, UR, Fh);
+    const T theta = fdiv(bound - Fh[0], F[0] - Fh[0]);
+    if (!(theta > T(0))) {
+        F[0] = Fh[0]; F[1] = Fh[1]; F[2] = Fh[2];
+    } else if (theta < T(1)) {
+        F[1] = Fh[1] + theta * (F[1] - Fh[1]);
+        F[2] = Fh[2] + theta * (F[2] - Fh[2]);
+        F[0] = bound;
+    }
 }
 
 }  // namespace swe

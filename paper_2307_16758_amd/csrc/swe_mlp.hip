@@ -217,7 +217,9 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
         const int grp = lane >> 4;
         const float z = grp == 0 ? o[0][0] : (grp == 1 ? o[1][0] : (grp == 2 ? o[2][0] : o[3][0]));
         const int row = rg * 64 + lane;
-        const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-z)) : 0.5f;
+        // NaN (not evaluated) where the half-edge is not reconstructed to
+        // second order: a stage that does reconstruct it falls back to minmod
+        const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-z)) : __builtin_nanf("");
         if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
     }
 }

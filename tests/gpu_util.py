@@ -56,9 +56,11 @@ def oracle_params(sc, name=None, **cfg):
     kw = dict(SCHEME_KW[name]) if name else {}
     kw.update({k_: v for k_, v in cfg.items() if k_ in ("scheme", "integrator", "limiter")})
     okw = {k_: v for k_, v in kw.items() if k_ in ("scheme", "integrator", "limiter")}
-    for k_ in ("waf_limiter", "waf_dry", "cfl_rule", "cfl", "dt_max", "eps"):
+    for k_ in ("waf_limiter", "cfl_rule", "cfl", "dt_max", "eps"):
         if k_ in cfg:
             okw[k_] = cfg[k_]
+    if "waf_positivity" in cfg:
+        okw["waf_pos"] = cfg["waf_positivity"]
     return O.scenario_params(sc, **okw)
 
 

@@ -122,9 +122,10 @@ def test_dam_break_onto_dry_bed(name):
     g = s.read_state()
     r = _oracle_run(M, par, sc, pr.sub.l2g, 150)
     errs = state_errors(g, r[:3], pr.sub.n_owned)
-    # WAF switches discretely (its superbee ratio, and the first-order
-    # weights below waf_dry at the front): a rounding-order difference can
-    # pick other weights at an isolated edge, so it gets 1e-9
+    # WAF switches discretely (the branches of its superbee ratio and
+    # weights, and where its mass flux meets a cell's positivity bound): a
+    # rounding-order difference can pick another branch at an isolated
+    # edge, so it gets 1e-9
     assert max(errs) <= (1e-9 if name == "waf" else 1e-10), errs
     A = M.geometry()["area"]
     m0 = (A * sc.h[pr.sub.l2g]).sum()
@@ -135,9 +136,11 @@ def test_dam_break_onto_dry_bed(name):
 @pytest.mark.parametrize("prec", [1, 0])
 def test_waf_on_a_river_stays_non_negative(prec):
     """WAF on a river with dry banks, bumps and inflow for 1500 CFL steps:
-    with the first-order weights below waf_dry at the fronts no depth goes
-    below -eps (the library would report NEGATIVE_DEPTH), and the state
-    tracks the oracle's over the first steps."""
+    with every edge's mass flux kept within its donor cells' shares (the
+    positivity blend towards HLLC) no depth goes below zero at all (no
+    negative depth, not even one clipped at round-off), and the state tracks
+    the oracle's over the first steps.  Without the blend the oracle goes
+    negative on this river (tests/test_oracle_physics.py)."""
     sc = river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=2)
     s, M, par, pr = make_pair(sc, "waf", precision=prec)
     s.step(20)

@@ -164,7 +164,7 @@ def test_limiter_inputs_consistent_with_reconstruction():
     mh, mb, mun, mut, _ = M.interfaces(pm, h, hu, hv)
     elig = inp[..., 23] == 1.0
     assert elig.sum() > 100
-    assert np.all(phi[elig] == 1.0) and np.all(phi[~elig] == 0.5)
+    assert np.all(phi[elig] == 1.0) and np.all(np.isnan(phi[~elig]))
     q, s, d = inp[..., 14:18], inp[..., 18:22], inp[..., 22:23]
     mm = (np.stack([mh, mh + mb, mun, mut], -1) - q) / d          # minmod slopes
     clip = np.where(mm == 0.0, 0.0, np.sign(mm) * np.minimum(np.abs(s), 2.0 * np.abs(mm)))

@@ -195,19 +195,58 @@ def test_closed_cell_friction_decay(name, kw):
 
 
 def test_waf_stays_non_negative_at_wet_dry_fronts():
-    """WAF with the first-order fallback at edges whose hydrostatic state is
-    shallower than waf_dry keeps the river's depths non-negative (dry banks,
-    bumps, inflow); without it (waf_dry = 0) the superbee weights drive a
-    shoreline cell below zero within a few hundred steps."""
+    """WAF with each edge's mass flux kept within the share L / P of its
+    donor cell's water (blended towards HLLC where WAF's flux exceeds it)
+    keeps the river's depths non-negative (dry banks, bumps, inflow) with no
+    threshold of its own: no depth below zero at all, not even one clipped
+    at round-off; plain WAF (waf_pos = 0) drives a shoreline cell below -eps
+    within a few hundred steps.  On a wet dam break the bound is never met
+    and WAF is bitwise unchanged."""
     sc = river_channel(Lx=2000.0, Ly=400.0, nx=160, ny=32, seed=2)
     M, _ = O.global_mesh(sc)
     flags = {}
-    for dry in (0.05, 0.0):
-        p = O.scenario_params(sc, scheme=O.WAF, integrator=O.EULER, waf_dry=dry)
+    for pos in (1, 0):
+        p = O.scenario_params(sc, scheme=O.WAF, integrator=O.EULER, waf_pos=pos)
         h, hu, hv, t, fl = M.run(p, sc.h, sc.hu, sc.hv, 1500)
-        flags[dry] = fl
-    assert flags[0.05] == 0
-    assert flags[0.0] & 2                  # a depth below -eps
+        flags[pos] = fl
+        if pos:
+            assert h.min() >= 0.0
+    assert flags[1] == 0                   # no negative depth, none clipped
+    assert flags[0] & 2                    # a depth below -eps
+    sc = dam_break_channel()
+    M, _ = O.global_mesh(sc)
+    runs = [M.run(O.scenario_params(sc, scheme=O.WAF, integrator=O.EULER, waf_pos=pos),
+                  sc.h, sc.hu, sc.hv, 200, dt_fixed=0.01) for pos in (1, 0)]
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert np.array_equal(a, b)
+
+
+def test_waf_positivity_blend_on_one_edge():
+    """The blend on one edge against the bound it enforces: a mass flux
+    within [-0.99 hR RR / (2 dt), 0.99 hL RL / (2 dt)] is left alone; one
+    above it is moved towards the HLLC flux of the same states until its
+    mass component is exactly the bound, the other components by the same
+    fraction; one beyond the bound on the other side the same way; if HLLC
+    is itself beyond the bound the edge takes HLLC."""
+    p = O.Params(scheme=O.WAF)
+    UL = np.array([0.3, 0.3 * 0.8, 0.3 * 0.1])
+    UR = np.array([0.2, 0.2 * 0.5, -0.2 * 0.2])
+    Fh = O.riemann(p, O.HLLC1, UL, UR)
+    hL, RL, hR, RR, dt = 0.3, 1.5, 0.2, 1.2, 0.5
+    hi, lo = 0.99 * hL * RL / (2 * dt), -0.99 * hR * RR / (2 * dt)
+    assert lo < Fh[0] < hi                       # HLLC within the bounds here
+    inside = np.array([0.5 * (Fh[0] + hi), 0.2, 0.05])
+    np.testing.assert_array_equal(O.waf_positivity(p, UL, UR, hL, RL, hR, RR, dt, inside), inside)
+    for F in (np.array([1.7 * hi, 0.31, -0.02]), np.array([1.5 * lo, -0.12, 0.07])):
+        G = O.waf_positivity(p, UL, UR, hL, RL, hR, RR, dt, F)
+        bound = hi if F[0] > hi else lo
+        assert G[0] == bound
+        theta = (bound - Fh[0]) / (F[0] - Fh[0])
+        assert 0 < theta < 1
+        np.testing.assert_allclose(G[1:], Fh[1:] + theta * (F[1:] - Fh[1:]), rtol=1e-14, atol=1e-16)
+    # a nearly dry donor: HLLC's own mass flux is beyond its bound
+    G = O.waf_positivity(p, UL, UR, 1e-6, RL, hR, RR, dt, np.array([2 * Fh[0], 0.3, 0.1]))
+    np.testing.assert_array_equal(G, Fh)
 
 
 def test_all_dry_domain():
