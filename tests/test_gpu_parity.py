@@ -82,7 +82,10 @@ def test_river_muscl_fp32_1000_steps(cell_kernel, block):
 @pytest.mark.parametrize("cell_kernel", [0, 1])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-10), (0, 1e-3)])
 def test_dam_break_waf(prec, tol, cell_kernel):
-    """WAF (superbee weights) on a 2D dam break, tiled and cell kernels."""
+    """WAF (superbee weights) on a 2D dam break, tiled and cell kernels, 60
+    steps: FP64 within 1e-10; FP32 within 1e-3 (WAF-superbee amplifies the
+    rounding of every step: a 1e-7 perturbation reaches about 1e-4 after 60
+    steps in the FP64 oracle itself, so 1e-4 cannot be held here)."""
     sc = dam_break_channel(Lx=50.0, Ly=10.0, nx=100, ny=20, x_dam=25.0)
     s, M, par, pr = make_pair(sc, "waf", precision=prec, cell_kernel=cell_kernel)
     l2g = pr.sub.l2g
@@ -91,6 +94,28 @@ def test_dam_break_waf(prec, tol, cell_kernel):
     errs = state_errors(g, r[:3], pr.sub.n_owned)
     print("waf", prec, errs)
     assert max(errs) <= tol, errs
+
+
+@pytest.mark.parametrize("cell_kernel", [0, 1])
+def test_waf_fp32_long_run_invariants(cell_kernel):
+    """FP32 WAF over 1000 steps of the wet dam break between walls.  WAF with
+    the superbee weights amplifies round-off (tests/test_oracle_physics.py:
+    the FP64 oracle itself turns a 1e-7 perturbation into 1e-2 within 200
+    steps), so the FP32 state cannot follow the oracle pointwise for long;
+    what holds at any length: exact mass conservation to FP32 rounding, no
+    negative or non-finite depth, and the solution staying within the
+    oracle's range of depths."""
+    sc = dam_break_channel(Lx=50.0, Ly=10.0, nx=100, ny=20, x_dam=25.0)
+    s, M, par, pr = make_pair(sc, "waf", precision=0, cell_kernel=cell_kernel)
+    l2g = pr.sub.l2g
+    dt = M.dt(par, sc.h[l2g], sc.hu[l2g], sc.hv[l2g])
+    g, r = _run_both(s, M, par, sc, l2g, 1000, dt_fixed=dt)
+    assert s.health() == 0
+    A = M.geometry()["area"]
+    m0 = (A * sc.h[l2g]).sum()
+    assert abs((A * g[0].astype(np.float64)).sum() - m0) <= 1e-6 * m0
+    assert g[0].min() >= 0.0 and np.isfinite(g[0]).all()
+    assert g[0].max() <= r[0].max() * 1.05 and g[0].min() >= r[0].min() * 0.95
 
 
 @pytest.mark.parametrize("name", ["hllc1", "muscl_minmod_rk2", "waf"])
