@@ -210,8 +210,15 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
+        # a gather-like read: 16 bytes out of every 128-byte line (one
+        # reduction kernel), to check that the byte counters count whole
+        # lines for scattered accesses too
+        lines = src.view(-1, 32)[:, :4]
+        part = lines.sum(dtype=torch.float32)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5,
+                          "strided_read_lines": n // 32, "strided_read_line_bytes": 128 * (n // 32),
+                          "strided_sum": float(part)}))
         return
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the path measured is one GPU's "

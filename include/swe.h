@@ -219,13 +219,16 @@ int swe_scenario_times(swe_ctx *ctx, double *t);  /* [n_scenarios]; syncs */
 
 /* Autotuner: times n_steps CFL steps for each launch shape of the
  * configured stage kernel (64, 128, 256 or, FP32 tiled kernel only, 512
- * threads per block; one tile per block or a persistent grid of
- * 2048 / block blocks per compute unit; with 256-cell FP32 tiles, builds for
+ * threads per block; one tile per block or a persistent grid of the blocks
+ * the chip holds at once; with 256-cell FP32 tiles, builds for
  * 6 and 7 waves per SIMD) from the current state, keeps the fastest and
  * restores the state, clocks and time.  The choice never changes results
  * (the tiled kernel is bitwise independent of the tiling, and both builds
  * perform the same operations).
- * Outputs may be NULL. */
+ * Outputs may be NULL; *persistent_grid is the chosen grid (-1: one tile per
+ * block).  Untuned contexts sweep tiles with a persistent grid of the blocks
+ * the chip holds at once when a launch has 8 or more rounds of tiles, and
+ * launch one tile per block otherwise. */
 int swe_autotune(swe_ctx *ctx, int n_steps, int *block, int *persistent_grid);
 
 /* n_steps explicit steps, asynchronous on the context's stream.

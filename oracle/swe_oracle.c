@@ -493,9 +493,10 @@ double or_mlp_loss_grad(const double *params, int n, const double *x, const doub
 /* ------------------------------------------------------------------------
  * Features of one half-edge for the learned limiter.  For each of h, q_n, q_t
  * (discharges in the edge frame) and b: tanh of the upwind and cross-edge
- * slopes made dimensionless with
- * the distance to the edge midpoint and the variable's scale, and their
- * clipped ratio; then the cell Froude number and the relative depth jump.
+ * increments over the distance to the edge midpoint (slope times d_mid)
+ * made dimensionless with the variable's scale, and the clipped ratio of
+ * the two increments; then the cell Froude number and the relative depth
+ * jump.
  * scale: h and b -> h_c + 0.01 m; q_n, q_t -> h_c * sqrt(g h_c) + 0.01 m^2/s.
  * ---------------------------------------------------------------------- */
 static void halfedge_features(double g, const double qc[4], const double qu[4],
@@ -505,10 +506,12 @@ static void halfedge_features(double g, const double qc[4], const double qu[4],
     double sh = hc + 0.01, sq = hc * sqrt(g * dmax(hc, 0.0)) + 0.01;
     double sc[4] = {sh, sq, sq, sh};
     for (int k = 0; k < 4; ++k) {
-        double sb = (qc[k] - qu[k]) / du, sf = (qf[k] - qc[k]) / df;
-        f[3 * k + 0] = tanh(sb * dm / sc[k]);
-        f[3 * k + 1] = tanh(sf * dm / sc[k]);
-        double r = sb * sf / (sf * sf + 1e-12);
+        /* the upwind and cross-edge increments over the distance to the edge
+         * midpoint: slope times d_mid */
+        double ab = (qc[k] - qu[k]) / du * dm, af = (qf[k] - qc[k]) / df * dm;
+        f[3 * k + 0] = tanh(ab / sc[k]);
+        f[3 * k + 1] = tanh(af / sc[k]);
+        double r = ab * af / (af * af + 1e-12);
         f[3 * k + 2] = dmax(-2.0, dmin(2.0, r));
     }
     f[12] = tanh(sqrt(uc * uc + vc * vc) / sqrt(g * dmax(hc, 1e-6)));

@@ -21,7 +21,7 @@ struct swe_ctx {
     int send_prefix = 0;  // the send cells are local cells [0, send_prefix)
     size_t tsize = 4;
     // device buffers
-    void *nbr = nullptr, *cell = nullptr, *he_geo = nullptr, *he_dist = nullptr;
+    void *nbr = nullptr, *cell = nullptr, *man2 = nullptr, *he_geo = nullptr, *he_dist = nullptr;
     void *he_co = nullptr, *he_lam = nullptr, *he_gam = nullptr;  // tiled kernel's half-edge set
     void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
     float *phi = nullptr;       // learned-limiter output, one per half-edge

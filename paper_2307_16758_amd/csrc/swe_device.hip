@@ -323,6 +323,7 @@ template <typename T> struct StageArgs {
     int n, n_scen;
     const int4 *nbr;
     const T4 *cell, *he_geo, *he_dist;
+    const T *man2;  // Manning n^2 per cell (tiled MUSCL kernel: its only per-cell record)
     // per half-edge, edge-major (m * n + c): nx, ny, d_mid / d_up, d_mid / d_fwd;
     // L / area; d_mid / d_central
     const T4 *he_co;
@@ -899,7 +900,7 @@ k_stage_tiled(StageArgs<T> a)
                                      a.dt_max, a.dt_fixed);
         if (active) {
             const T dt = T(dtd);
-            T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+            T acc0 = T(0), acc1 = T(0), acc2 = T(0), lsum = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const T lam = ldx(a.he_lam, m * a.n + c);
@@ -907,11 +908,17 @@ k_stage_tiled(StageArgs<T> a)
                 acc0 += lam * f.x;
                 acc1 += lam * f.y;
                 acc2 += lam * f.z;
+                lsum += lam;
             }
             T nh = Uc.x - dt * acc0;
             T nu = Uc.y - dt * acc1;
             T nv = Uc.z - dt * acc2;
-            const T4 cg = ldx(a.cell, c);
+            // the inscribed radius from the edge weights: sum_m L_m / |Omega|
+            // = P / |Omega|, so R = 2 |Omega| / P = 2 / that sum; Manning's
+            // n^2 is the only per-cell value read (4 bytes, not 16)
+            T4 cg;
+            cg.y = fdiv(T(2), lsum);
+            cg.z = ldx(a.man2, c);
             int flags = 0;
             if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
             if (nh < T(0)) {
@@ -1310,7 +1317,7 @@ template <typename P> void dfree_t(swe_ctx *c, P *&p)
 void release_mesh(swe_ctx *c)
 {
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
-    dfree(c, c->nbr); dfree(c, c->cell); dfree(c, c->he_geo); dfree(c, c->he_dist);
+    dfree(c, c->nbr); dfree(c, c->cell); dfree(c, c->man2); dfree(c, c->he_geo); dfree(c, c->he_dist);
     dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam);
     dfree(c, c->U[0]); dfree(c, c->U[1]); dfree(c, c->U1); dfree(c, c->tmp3); dfree(c, c->bed);
     dfree_t(c, c->phi); dfree_t(c, c->clock); dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
@@ -1340,6 +1347,12 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
     to_t(g.cell, tmp);
     HIP_OK(c, dalloc(c, (void **)&c->cell, 4 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->cell, tmp.data(), 4 * sizeof(T) * n, hipMemcpyHostToDevice));
+    {
+        std::vector<T> m2(n);
+        for (size_t i = 0; i < n; ++i) m2[i] = tmp[4 * i + 2];
+        HIP_OK(c, dalloc(c, (void **)&c->man2, sizeof(T) * n));
+        HIP_OK(c, hipMemcpy(c->man2, m2.data(), sizeof(T) * n, hipMemcpyHostToDevice));
+    }
     to_t(g.he_geo, tmp);
     HIP_OK(c, dalloc(c, (void **)&c->he_geo, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_geo, tmp.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
@@ -1482,6 +1495,15 @@ template <typename T> KernelFn<T> pick_cell_kernel(int scheme, int lim, int wafm
     }
 }
 
+// Blocks of `kernel` (block size B) the whole chip holds at once (0 if the
+// occupancy query fails).
+inline int resident_blocks(const swe_ctx *c, const void *kernel, int B)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, B, 0) != hipSuccess) return 0;
+    return per_cu * c->ncu;
+}
+
 // Fused pack of the high-overlap step: the send buffer the last stage fills
 struct OverlapPlan {
     void *sendbuf = nullptr;  // null: a plain step
@@ -1496,6 +1518,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     a.n_scen = c->n_scen;
     a.nbr = (const int4 *)c->nbr;
     a.cell = (const T4 *)c->cell;
+    a.man2 = (const T *)c->man2;
     a.he_geo = (const T4 *)c->he_geo;
     a.he_dist = (const T4 *)c->he_dist;
     a.he_co = (const T4 *)c->he_co;
@@ -1529,7 +1552,17 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B,
                                    cell_kernel, seven_waves<T>(c, B), euler);
     const int ntiles = (c->n_total + B - 1) / B;
-    const dim3 grid(c->grid_persist > 0 && c->grid_persist < ntiles ? c->grid_persist : ntiles);
+    int gp = c->grid_persist;
+    if (gp == 0 && !cell_kernel) {
+        // many rounds of tiles (8 or more): a persistent grid of the blocks
+        // the chip holds at once, each sweeping tiles (measured: 2.7% faster
+        // on the 13M-cell river; on a mesh of a few rounds the hardware's
+        // own dispatch of one tile per block balances better)
+        const int res = resident_blocks(c, (const void *)k, B);
+        if (res > 0 && ntiles >= 8 * res) gp = res;
+    }
+    if (gp < 0) gp = 0;  // one tile per block, as asked
+    const dim3 grid(gp > 0 && gp < ntiles ? gp : ntiles);
     const dim3 blk(B);
     T4 *Ucur = (T4 *)c->U[step & 1];
     const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
@@ -2140,7 +2173,14 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
         for (int persist = 0; persist < 2 && rc == SWE_OK; ++persist) {
             c->block = B;
             c->waves = W;
-            c->grid_persist = persist ? ncu * (2048 / B) : 0;
+            c->grid_persist = -1;  // one tile per block
+            if (persist) {
+                const bool cell = c->cfg.cell_kernel || (c->cfg.scheme == SWE_WAF && c->cfg.integrator != SWE_EULER);
+                const int res = c->cfg.precision == SWE_F64
+                                    ? resident_blocks(c, (const void *)pick_kernel<double>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B, cell, false, c->cfg.integrator == SWE_EULER), B)
+                                    : resident_blocks(c, (const void *)pick_kernel<float>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B, cell, W == 7, c->cfg.integrator == SWE_EULER), B);
+                c->grid_persist = res > 0 ? res : ncu * (2048 / B);
+            }
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
             c->step_count = step0;

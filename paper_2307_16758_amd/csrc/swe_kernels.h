@@ -341,17 +341,18 @@ constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlp
 
 // Inputs of the learned limiter for the half-edge of cell c across local
 // edge m (a design of this library; the paper has no learned limiter): for
-// h, q_n, q_t (discharges in the edge frame) and b, the upwind slope sb and
-// the cross-edge slope sf as tanh(s d_mid / scale) and their ratio
-// sb sf / (sf^2 + 1e-12) clipped to [-2, 2]; then tanh of the cell's Froude
+// h, q_n, q_t (discharges in the edge frame) and b, the upwind and
+// cross-edge increments to the edge midpoint ab = sb d_mid and af = sf d_mid
+// as tanh(a / scale) and their ratio ab af / (af^2 + 1e-12) clipped to
+// [-2, 2]; then tanh of the cell's Froude
 // number and of the relative depth jump across the edge.  Scales: h, b:
 // h_c + 0.01 m; q: h_c sqrt(g h_c) + 0.01 m^2/s.  Returns false when the
 // half-edge is not reconstructed to second order (dry stencil cell, no
 // neighbour across the edge, no upwind cell): the features are then zero.
 template <typename T, typename T4>
 __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, bool hk_, const T4 &Ua,
-                                                 bool ha, const T4 &Ub, bool hb, T nx, T ny, T dm,
-                                                 const T4 &dist, T g, T eps, float f[kMlpIn])
+                                                 bool ha, const T4 &Ub, bool hb, T nx, T ny, T al,
+                                                 T be, T g, T eps, float f[kMlpIn])
 {
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) f[i] = 0.0f;
@@ -374,11 +375,14 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
     const T sc[4] = {sh, sq, sq, sh};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const T sb = (qc[k] - qu[k]) * dist.x, sf = (qk[k] - qc[k]) * dist.y;
+        // upwind and cross-edge increments over the distance to the edge
+        // midpoint (slope times d_mid): the MUSCL weights al = d_mid / d_up
+        // and be = d_mid / d_fwd times the differences
+        const T ab = al * (qc[k] - qu[k]), af = be * (qk[k] - qc[k]);
         const T isc = frcp(sc[k]);
-        f[3 * k + 0] = float(ftanh(sb * dm * isc));
-        f[3 * k + 1] = float(ftanh(sf * dm * isc));
-        const T r = fdiv(sb * sf, sf * sf + T(1e-12));
+        f[3 * k + 0] = float(ftanh(ab * isc));
+        f[3 * k + 1] = float(ftanh(af * isc));
+        const T r = fdiv(ab * af, af * af + T(1e-12));
         f[3 * k + 2] = float(tmin(T(2), tmax(T(-2), r)));
     }
     const T ih = frcp(hc);

@@ -101,7 +101,7 @@ template <typename T> struct PhiArgs {
     using T4 = typename V4<T>::type;
     int n;
     const int4 *nbr;
-    const T4 *he_geo, *he_dist, *U;
+    const T4 *he_co, *U;  // he_co: nx, ny, d_mid / d_up, d_mid / d_fwd per half-edge (edge-major)
     const MlpDev *w;
     float *phi;
     T g, eps;
@@ -141,8 +141,6 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const int ma = (m + 1) % 3, mb = (m + 2) % 3;
-            const T4 ge = a.he_geo[3 * c + m];
-            const T4 di = a.he_dist[3 * c + m];
             const T4 Um = m == 0 ? Un0 : (m == 1 ? Un1 : Un2);
             const T4 Ua = ma == 0 ? Un0 : (ma == 1 ? Un1 : Un2);
             const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
@@ -150,8 +148,9 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
             const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
             const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
             float f[kMlpIn];
-            const bool ok = limiter_features<T, T4>(Uc, Um, hm, Ua, ha, Ub, hb, ge.x, ge.y, ge.w, di,
-                                                    a.g, a.eps, f);
+            const T4 co = a.he_co[m * a.n + c];
+            const bool ok = limiter_features<T, T4>(Uc, Um, hm, Ua, ha, Ub, hb, co.x, co.y, co.z,
+                                                    co.w, a.g, a.eps, f);
 #pragma unroll
             for (int i = 0; i < kMlpIn; ++i) X[wv][3 * lane + m][i] = bf16_bits_hw(f[i]);
             // column 14 is padding; column 15 (zero weights) flags an eligible half-edge
@@ -249,7 +248,7 @@ template <typename T> struct PairArgs {
     using T4 = typename V4<T>::type;
     int n;
     const int4 *nbr;
-    const T4 *he_geo, *he_dist, *U, *Uf;
+    const T4 *he_geo, *he_dist, *he_co, *U, *Uf;
     const int *children;
     int n_fine;
     float *rec;
@@ -281,8 +280,9 @@ __global__ void k_pairs(PairArgs<T> a)
         const T4 di = a.he_dist[3 * c + m];
         const T nx = ge.x, ny = ge.y;
         float f[kMlpIn];
-        bool ok = limiter_features<T, T4>(Uc, Un[m], hn[m], Un[ma], hn[ma], Un[mb], hn[mb], nx, ny,
-                                          ge.w, di, a.g, eps, f);
+        const T4 co = a.he_co[m * a.n + c];
+        bool ok = limiter_features<T, T4>(Uc, Un[m], hn[m], Un[ma], hn[ma], Un[mb], hn[mb], co.x, co.y,
+                                          co.z, co.w, a.g, eps, f);
         for (int i = 0; i < kMlpIn; ++i) r[i] = f[i];
         T qc[4] = {Uc.x, Uc.x + Uc.w, T(0), T(0)};
         frame_vel(Uc, nx, ny, eps, qc[2], qc[3]);
@@ -525,14 +525,12 @@ int launch_limiter_phi(swe_ctx *c, const void *U)
     if (!c->has_mlp) return err(c, SWE_ERR_STATE, "learned limiter weights not set");
     const int n = c->n_total, B = 256, G = (n + B - 1) / B;
     if (c->tsize == 8) {
-        PhiArgs<double> a{n, (const int4 *)c->nbr, (const double4 *)c->he_geo,
-                          (const double4 *)c->he_dist, (const double4 *)U, (const MlpDev *)c->mlp,
-                          c->phi, c->cfg.g, c->cfg.eps};
+        PhiArgs<double> a{n, (const int4 *)c->nbr, (const double4 *)c->he_co, (const double4 *)U,
+                          (const MlpDev *)c->mlp, c->phi, c->cfg.g, c->cfg.eps};
         hipLaunchKernelGGL(k_limiter_phi<double>, dim3(G), dim3(B), 0, c->stream, a);
     } else {
-        PhiArgs<float> a{n, (const int4 *)c->nbr, (const float4 *)c->he_geo,
-                         (const float4 *)c->he_dist, (const float4 *)U, (const MlpDev *)c->mlp,
-                         c->phi, (float)c->cfg.g, (float)c->cfg.eps};
+        PhiArgs<float> a{n, (const int4 *)c->nbr, (const float4 *)c->he_co, (const float4 *)U,
+                         (const MlpDev *)c->mlp, c->phi, (float)c->cfg.g, (float)c->cfg.eps};
         hipLaunchKernelGGL(k_limiter_phi<float>, dim3(G), dim3(B), 0, c->stream, a);
     }
     return hipGetLastError() == hipSuccess ? SWE_OK : err(c, SWE_ERR_DEVICE, "limiter launch failed");
@@ -589,7 +587,8 @@ int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_childre
                            fine->n_total, (const double4 *)Uf, (const double *)coarse->bed,
                            (double4 *)Uc, coarse->flag);
         PairArgs<double> a{n, (const int4 *)coarse->nbr, (const double4 *)coarse->he_geo,
-                           (const double4 *)coarse->he_dist, (const double4 *)Uc, (const double4 *)Uf,
+                           (const double4 *)coarse->he_dist, (const double4 *)coarse->he_co,
+                           (const double4 *)Uc, (const double4 *)Uf,
                            dev_children, fine->n_total, dev_rec, coarse->cfg.g, coarse->cfg.eps};
         hipLaunchKernelGGL(k_pairs<double>, dim3(G), dim3(B), 0, coarse->stream, a);
     } else {
@@ -597,7 +596,8 @@ int swe_limiter_pairs(swe_ctx *coarse, swe_ctx *fine, const int32_t *dev_childre
                            fine->n_total, (const float4 *)Uf, (const float *)coarse->bed,
                            (float4 *)Uc, coarse->flag);
         PairArgs<float> a{n, (const int4 *)coarse->nbr, (const float4 *)coarse->he_geo,
-                          (const float4 *)coarse->he_dist, (const float4 *)Uc, (const float4 *)Uf,
+                          (const float4 *)coarse->he_dist, (const float4 *)coarse->he_co,
+                          (const float4 *)Uc, (const float4 *)Uf,
                           dev_children, fine->n_total, dev_rec, (float)coarse->cfg.g,
                           (float)coarse->cfg.eps};
         hipLaunchKernelGGL(k_pairs<float>, dim3(G), dim3(B), 0, coarse->stream, a);
