@@ -192,6 +192,9 @@ def main():
     ap.add_argument("--limiter", choices=("minmod", "learned"), default="minmod",
                     help="learned: the per-edge network (untrained weights: its cost, not its "
                          "accuracy) ahead of every stage")
+    ap.add_argument("--phi-in-stage", type=int, default=0,
+                    help="learned limiter: 1 evaluates the network inside the first stage "
+                         "instead of in a kernel of its own ahead of each step")
     ap.add_argument("--snapshot-every", type=int, default=0, metavar="M",
                     help="take the state to pinned host memory every M steps (swe_snapshot, "
                          "copied on a side stream while the steps go on), inside the timed region")
@@ -234,7 +237,8 @@ def main():
         kw = dict(kw, scheme=2 if args.scheme == "waf" else 0, integrator=0)
     if args.limiter == "learned":
         kw = dict(kw, limiter=swe.LEARNED)
-    s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel, **kw)
+    s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel,
+                   phi_in_stage=args.phi_in_stage, **kw)
     mlp = None
     if args.limiter == "learned":
         from paper_2307_16758_amd.limiter_train import init_params

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 3
+#define SWE_ABI_VERSION 4
 
 /* status codes */
 #define SWE_OK 0
@@ -135,7 +135,13 @@ typedef struct {
                           (R the inscribed radius, i.e. the edge's share L / P of the
                           cell's water per step); a WAF flux beyond it is blended
                           towards the HLLC flux of the same states; 0: plain WAF */
-    int reserved1;
+    int phi_in_stage;  /* SWE_LEARNED with the tiled kernel: 0 (default) evaluates the
+                          network in a kernel of its own ahead of each step; 1 evaluates
+                          it inside the step's first stage (phi stored for the second;
+                          the far side of a tile-crossing edge evaluated where it is
+                          needed), which saves that kernel's loads but adds its
+                          arithmetic to a stage that is already half arithmetic-bound:
+                          slower on the meshes measured.  Same results either way. */
 } swe_config;
 
 /* One sub-domain (or a whole mesh: n_owned == n_total, n_peers == 0).

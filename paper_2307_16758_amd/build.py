@@ -28,9 +28,11 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-ffp-contract=on",
              "-Wno-unused-result"] + os.environ.get("SWE_EXTRA_HIPFLAGS", "").split()
 
-# per source: the network kernels keep MFMA accumulators in ordinary vector
-# registers (no moves out of accumulation registers between layers)
-FILE_FLAGS = {"swe_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# per source: the network (in its own kernel and in the stage kernel that
+# evaluates it) keeps MFMA accumulators in ordinary vector registers (no
+# moves out of accumulation registers between layers)
+FILE_FLAGS = {"swe_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+              "swe_device.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def run(cmd):

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "swe_ctx.h"
+#include "swe_mlp_dev.h"
 #include "swe_internal.h"
 #include "swe_kernels.h"
 
@@ -334,7 +335,11 @@ template <typename T> struct StageArgs {
     int ncopy;                   // CFL partial copies per clock slot (power of two <= 64)
     const ScenParams *scen;
     const double *ser_t, *ser_q;
-    const float *phi;
+    // learned limiter: phi per half-edge (3 c + m), stored by the instance
+    // of the tiled stage that evaluates the network (the step's first
+    // stage), read by the others
+    float *phi;
+    const MlpDev *mlp;
     int *health;
     T g, eps;
     int waf_pos;  // WAF: mass fluxes kept within the donor cells' shares (waf_positivity)
@@ -711,15 +716,23 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs<T> a)
 // reads no global memory for edges inside the tile but the normal.  Half-edge
 // slots are local-edge-major (slot of cell l, edge m at m * TILE + l), so a
 // wave's per-cell accesses are consecutive.
+// Learned limiter in the step's first stage: the tiled instance that also
+// evaluates the network and stores phi (the second stage reads it)
+constexpr int kLearnedNet = 5;
 #ifndef SWE_TILED_WAVES
 #define SWE_TILED_WAVES 6  // FP32: waves per SIMD the register budget is sized for
 #endif
 #ifndef SWE_TILED_WAVES_LEARNED
 #define SWE_TILED_WAVES_LEARNED 5  // the learned-limiter instance needs 96 registers
 #endif
+#ifndef SWE_TILED_WAVES_NET
+#define SWE_TILED_WAVES_NET 4  // the instance that also evaluates the network (128 registers)
+#endif
 template <typename T, bool MUSCL_, int LIM, int TILE, int OCC = SWE_TILED_WAVES>
 __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 ? (LIM == kLearned ? SWE_TILED_WAVES_LEARNED : OCC) : 2)))
+    sizeof(T) == 4 ? (LIM == kLearned ? SWE_TILED_WAVES_LEARNED
+                                      : (LIM == kLearnedNet ? SWE_TILED_WAVES_NET : OCC))
+                   : 2)))
 k_stage_tiled(StageArgs<T> a)
 {
     using T4 = typename V4<T>::type;
@@ -735,6 +748,12 @@ k_stage_tiled(StageArgs<T> a)
     __shared__ unsigned sW[TILE];      // packed word of each cell
     __shared__ int sCount[2];
     __shared__ CflVal<T> sCfl[TILE / 64];
+    // learned limiter: kNet evaluates phi (input rows of the network in LDS,
+    // 64 per wave), kLrn reads it; RL is the limiter of the reconstruction
+    constexpr bool kNet = MUSCL_ && LIM == kLearnedNet;
+    constexpr bool kLrn = MUSCL_ && (LIM == kLearned || LIM == kLearnedNet);
+    constexpr int RL = LIM == kLearnedNet ? kLearned : LIM;
+    __shared__ __align__(16) uint16_t sX[kNet ? TILE : 1][16];
     clock_upkeep(a);
     const T g = a.g, eps = a.eps;
     const int ntiles = (a.n + TILE - 1) / TILE;
@@ -750,7 +769,99 @@ k_stage_tiled(StageArgs<T> a)
         dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur, active ? (int)((unsigned)nb4.w >> kScenShift) : -1,
                           a.dt_fixed);
         T4 Ukeep;  // the cell's state, kept for phase 3
-        if (active) {
+        if constexpr (kLrn) {
+            // phi of the cell's three half-edges: in the step's first stage
+            // from the network on U^n (the wave evaluates its 64 half-edges
+            // of one local edge at a time) and stored for the second, else
+            // the stored values
+            const bool hn0 = active && nb4.x >= 0, hn1 = active && nb4.y >= 0, hn2 = active && nb4.z >= 0;
+            float ph[3] = {0.0f, 0.0f, 0.0f};
+            if constexpr (kNet) {
+                T4 Uc{}, Un0{}, Un1{}, Un2{}, co0{}, co1{}, co2{};
+                if (active) {
+                    Uc = ldx(a.Uin, c);
+                    Un0 = ldx(a.Uin, hn0 ? nb4.x : c);
+                    Un1 = ldx(a.Uin, hn1 ? nb4.y : c);
+                    Un2 = ldx(a.Uin, hn2 ? nb4.z : c);
+                    co0 = ldx(a.he_co, c);
+                    co1 = ldx(a.he_co, a.n + c);
+                    co2 = ldx(a.he_co, 2 * a.n + c);
+                }
+                const int lane = threadIdx.x & 63;
+                uint16_t(*X)[16] = sX + (threadIdx.x & ~63);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+                    const T4 Um = m == 0 ? Un0 : (m == 1 ? Un1 : Un2);
+                    const T4 Ua = ma == 0 ? Un0 : (ma == 1 ? Un1 : Un2);
+                    const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
+                    const bool hm = m == 0 ? hn0 : (m == 1 ? hn1 : hn2);
+                    const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
+                    const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
+                    const T4 co = m == 0 ? co0 : (m == 1 ? co1 : co2);
+                    float f[kMlpIn];
+                    const bool ok = limiter_features<T, T4>(Uc, Um, hm, Ua, ha, Ub, hb, co.x, co.y,
+                                                            co.z, co.w, g, eps, f);
+                    mlp_write_row(X[lane], f, ok);
+                    wave_lds_sync();
+                    // the weights are loaded where they are used (L1 hits), so
+                    // that they do not hold registers across the features
+                    const MlpLane L = mlp_lane(a.mlp, lane);
+                    ph[m] = mlp_phi(mlp_rows_z(L, X, lane), ok);
+                    wave_lds_sync();  // the rows are rewritten for the next edge
+                    if (active) a.phi[3 * c + m] = ph[m];
+                }
+            } else if (active) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) ph[m] = ldx(a.phi, 3 * c + m);
+            }
+            T4 Uc{}, Un0{}, Un1{}, Un2{}, co0{}, co1{}, co2{};
+            if (active) {
+                Uc = ldx(a.Uin, c);
+                Un0 = ldx(a.Uin, hn0 ? nb4.x : c);
+                Un1 = ldx(a.Uin, hn1 ? nb4.y : c);
+                Un2 = ldx(a.Uin, hn2 ? nb4.z : c);
+                co0 = ldx(a.he_co, c);
+                co1 = ldx(a.he_co, a.n + c);
+                co2 = ldx(a.he_co, 2 * a.n + c);
+            }
+            if (active) {
+                Ukeep = Uc;
+                const unsigned word = (unsigned)nb4.w;
+                sW[cl] = word;
+                const Prim<T> pc = prim(Uc, eps);
+                // a missing neighbour's slot holds the cell's own state
+                const Prim<T> pn[3] = {prim(Un0, eps), prim(Un1, eps), prim(Un2, eps)};
+                const bool hn[3] = {hn0, hn1, hn2};
+                const int nb[3] = {nb4.x, nb4.y, nb4.z};
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const int k = nb[m];
+                    sK[m * TILE + cl] = k;
+                    const unsigned jb = (word >> (2 * m)) & 3u, isL = (word >> (6 + m)) & 1u;
+                    const unsigned ent = (unsigned)m | ((unsigned)cl << 2) | (jb << 12) | (isL << 14);
+                    if (k < 0) {  // boundary half-edge: a task of its own
+                        sTask[atomicAdd(&sCount[0], 1)] = ent;
+                        continue;
+                    }
+                    const T4 co = m == 0 ? co0 : (m == 1 ? co1 : co2);
+                    const T ga = ldx(a.he_gam, m * a.n + c);
+                    const int ma = (m + 1) % 3, mb = (m + 2) % 3;
+                    const Half<T> r = recon3<T, MUSCL_, RL>(pc, pn[m], pn[ma], hn[ma], pn[mb], hn[mb],
+                                                             co.x, co.y, co.z, co.w, ga, ph[m], eps);
+                    T4 rv;
+                    rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
+                    sR[m * TILE + cl] = rv;
+                    sB[m * TILE + cl] = T(0.5) * g * (r.h + Uc.x) * (r.eta - (pc.h + pc.b));
+                    const int kl = k - c0;
+                    if (kl >= 0 && kl < TILE) {
+                        if (isL) sTask[3 * TILE - 1 - atomicAdd(&sCount[1], 1)] = ent | ((unsigned)kl << 15);
+                    } else {
+                        sTask[atomicAdd(&sCount[0], 1)] = ent;
+                    }
+                }
+            }
+        } else if (active) {
             const T4 Uc = ldx(a.Uin, c);
             Ukeep = Uc;
             const int nb[3] = {nb4.x, nb4.y, nb4.z};
@@ -775,12 +886,9 @@ k_stage_tiled(StageArgs<T> a)
                     continue;
                 }
                 const T4 co = ldx(a.he_co, m * a.n + c);
-                T ga = T(0);
-                float phi = 0.0f;
-                if (MUSCL_ && LIM == kLearned) { ga = ldx(a.he_gam, m * a.n + c); phi = ldx(a.phi, 3 * c + m); }
                 const int ma = (m + 1) % 3, mb = (m + 2) % 3;
                 const Half<T> r = recon3<T, MUSCL_, LIM>(pc, pn[m], pn[ma], hn[ma], pn[mb], hn[mb],
-                                                          co.x, co.y, co.z, co.w, ga, phi, eps);
+                                                          co.x, co.y, co.z, co.w, T(0), 0.0f, eps);
                 T4 rv;
                 rv.x = r.h; rv.y = r.b; rv.z = r.un; rv.w = r.ut;
                 sR[m * TILE + cl] = rv;
@@ -799,7 +907,47 @@ k_stage_tiled(StageArgs<T> a)
         // ---- 2: edge tasks, one dense sweep (outside-tile edges first)
         {
             const int n0 = sCount[0], nt = n0 + sCount[1];
-            for (int i = threadIdx.x; i < nt; i += TILE) {
+            // learned limiter: every thread runs the same number of sweeps,
+            // so that a wave evaluates the network as a whole
+            const int iend = kNet ? (nt + TILE - 1) / TILE * TILE : nt;
+            for (int i = threadIdx.x; i < iend; i += TILE) {
+                float phin = 0.0f;  // learned, first stage: phi of an outside edge's far side
+                if constexpr (kNet) {
+                    if (i - (int)threadIdx.x < n0) {
+                        // the far side's own half-edge, from its 1-ring of U^n
+                        // (the tile that owns it evaluates the same bits)
+                        T4 Uk{}, Ut{}, Ua{}, Ub{}, ck{};
+                        bool hk = false, ha = false, hb = false;
+                        if (i < n0) {
+                            const unsigned task = sTask[i];
+                            const int m = task & 3u, tl = (task >> 2) & 1023u, jb = (task >> 12) & 3u;
+                            const int k = sK[m * TILE + tl];
+                            if (k >= 0) {
+                                const int4 nk = ldx(a.nbr, k);
+                                const int ka = pick3(nk, (jb + 1) % 3), kb = pick3(nk, (jb + 2) % 3);
+                                hk = true;
+                                ha = ka >= 0;
+                                hb = kb >= 0;
+                                Uk = ldx(a.Uin, k);
+                                Ut = ldx(a.Uin, c0 + tl);
+                                Ua = ldx(a.Uin, ha ? ka : k);
+                                Ub = ldx(a.Uin, hb ? kb : k);
+                                ck = ldx(a.he_co, jb * a.n + k);
+                            }
+                        }
+                        float f[kMlpIn];
+                        const bool ok = limiter_features<T, T4>(Uk, Ut, hk, Ua, ha, Ub, hb, ck.x, ck.y,
+                                                                ck.z, ck.w, g, eps, f);
+                        const int lane = threadIdx.x & 63;
+                        uint16_t(*X)[16] = sX + (threadIdx.x & ~63);
+                        const MlpLane L = mlp_lane(a.mlp, lane);
+                        mlp_write_row(X[lane], f, ok);
+                        wave_lds_sync();
+                        phin = mlp_phi(mlp_rows_z(L, X, lane), ok);
+                        wave_lds_sync();
+                    }
+                    if (i >= nt) continue;
+                }
                 const bool inside = i >= n0;
                 const unsigned task = inside ? sTask[3 * TILE - 1 - (i - n0)] : sTask[i];
                 const int m = task & 3u, tl = (task >> 2) & 1023u, jb = (task >> 12) & 3u;
@@ -854,9 +1002,12 @@ k_stage_tiled(StageArgs<T> a)
                         const T4 ck = ldx(a.he_co, jb * a.n + k);
                         al = ck.z;
                         be = ck.w;
-                        if (LIM == kLearned) { ga = ldx(a.he_gam, jb * a.n + k); phik = ldx(a.phi, 3 * k + jb); }
+                        if (RL == kLearned) {
+                            ga = ldx(a.he_gam, jb * a.n + k);
+                            phik = kNet ? phin : ldx(a.phi, 3 * k + jb);
+                        }
                     }
-                    const Half<T> r = recon3<T, MUSCL_, LIM>(pk, pc, pka, hka, pkb, hkb, -nx, -ny, al,
+                    const Half<T> r = recon3<T, MUSCL_, RL>(pk, pc, pka, hka, pkb, hkb, -nx, -ny, al,
                                                               be, ga, phik, eps);
                     kv.x = r.h; kv.y = r.b; kv.z = r.un; kv.w = r.ut;
                 }
@@ -1426,6 +1577,7 @@ template <typename T, int TILE, int OCC = SWE_TILED_WAVES> KernelFn<T> pick_tile
     case kSuperbee: return k_stage_tiled<T, true, kSuperbee, TILE, OCC>;
     case kVanAlbada: return k_stage_tiled<T, true, kVanAlbada, TILE, OCC>;
     case kLearned: return k_stage_tiled<T, true, kLearned, TILE>;
+    case kLearnedNet: return k_stage_tiled<T, true, kLearnedNet, TILE>;
     case kZeroSlope: return k_stage_tiled<T, true, kZeroSlope, TILE, OCC>;
     default: return k_stage_tiled<T, true, kMinmod, TILE, OCC>;
     }
@@ -1504,6 +1656,22 @@ inline int resident_blocks(const swe_ctx *c, const void *kernel, int B)
     return per_cu * c->ncu;
 }
 
+// Blocks of a tiled stage launch: one per tile, or, when the configuration
+// asks for it or the launch spans many rounds of tiles (8 or more), a
+// persistent grid of the blocks the chip holds at once, each sweeping tiles
+// (measured: 2.7% faster on the 13M-cell river; on a mesh of a few rounds
+// the hardware's own dispatch of one tile per block balances better)
+inline int stage_grid(const swe_ctx *c, const void *kernel, int B, int ntiles)
+{
+    int gp = c->grid_persist;
+    if (gp == 0) {
+        const int res = resident_blocks(c, kernel, B);
+        if (res > 0 && ntiles >= 8 * res) gp = res;
+    }
+    if (gp < 0) gp = 0;  // one tile per block, as asked
+    return gp > 0 && gp < ntiles ? gp : ntiles;
+}
+
 // Fused pack of the high-overlap step: the send buffer the last stage fills
 struct OverlapPlan {
     void *sendbuf = nullptr;  // null: a plain step
@@ -1552,31 +1720,31 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     KernelFn<T> k = pick_kernel<T>(c->cfg.scheme, c->cfg.limiter, c->cfg.waf_limiter, B,
                                    cell_kernel, seven_waves<T>(c, B), euler);
     const int ntiles = (c->n_total + B - 1) / B;
-    int gp = c->grid_persist;
-    if (gp == 0 && !cell_kernel) {
-        // many rounds of tiles (8 or more): a persistent grid of the blocks
-        // the chip holds at once, each sweeping tiles (measured: 2.7% faster
-        // on the 13M-cell river; on a mesh of a few rounds the hardware's
-        // own dispatch of one tile per block balances better)
-        const int res = resident_blocks(c, (const void *)k, B);
-        if (res > 0 && ntiles >= 8 * res) gp = res;
-    }
-    if (gp < 0) gp = 0;  // one tile per block, as asked
-    const dim3 grid(gp > 0 && gp < ntiles ? gp : ntiles);
+    dim3 grid(cell_kernel ? ntiles : stage_grid(c, (const void *)k, B, ntiles));
     const dim3 blk(B);
     T4 *Ucur = (T4 *)c->U[step & 1];
+    // the learned limiter's phi is evaluated once per step, from U^n: by a
+    // kernel of its own ahead of the step, or (when the configuration asks
+    // for it, tiled kernel only) by the step's first stage
     const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
-    T4 *Unext = (T4 *)c->U[(step + 1) & 1];
+    const bool phi_sep = learned && (cell_kernel || !c->cfg.phi_in_stage);
+    a.mlp = (const MlpDev *)c->mlp;
+    if (phi_sep && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
+    KernelFn<T> k1 = k;  // the step's first stage
+    dim3 grid1 = grid;
+    if (learned && !phi_sep) {
+        k1 = pick_kernel<T>(c->cfg.scheme, kLearnedNet, c->cfg.waf_limiter, B, 0, false, euler);
+        grid1 = dim3(stage_grid(c, (const void *)k1, B, ntiles));
+    }
     if (c->cfg.integrator == SWE_RK2) {
-        // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2;
-        // the learned limiter's phi is evaluated once per step, from U^n
-        if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
+        // stage 1: U^n -> U1;  stage 2: U1 -> U^{n+1} = (U^n + E(U1)) / 2
         a.kind = 1; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U1;
-        hipLaunchKernelGGL(k, grid, blk, 0, c->stream, a);
+        hipLaunchKernelGGL(k1, grid1, blk, 0, c->stream, a);
         a.kind = 2; a.Uin = (T4 *)c->U1; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
     } else {
-        if (learned && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
         a.kind = 0; a.Uin = Ucur; a.U0 = Ucur; a.Uout = (T4 *)c->U[(step + 1) & 1];
+        k = k1;
+        grid = grid1;
     }
     if (ov.sendbuf && c->n_send > 0) {  // the last stage also fills the send buffer
         a.pk_off = c->pk_off;
@@ -1653,7 +1821,8 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->scheme < 0 || cfg->scheme > 2 || cfg->integrator < 0 || cfg->integrator > 1 ||
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
-        !(cfg->eps >= 0) || (cfg->waf_positivity != 0 && cfg->waf_positivity != 1) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+        !(cfg->eps >= 0) || (cfg->waf_positivity != 0 && cfg->waf_positivity != 1) ||
+        (cfg->phi_in_stage != 0 && cfg->phi_in_stage != 1) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
         (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7) || (!cfg->alloc != !cfg->free))
@@ -2067,8 +2236,8 @@ int swe_step_kernel(const swe_ctx *c, const char **name, int *launches_per_step)
     const int stages = euler ? 1 : 2;
     if (cell_kernel) *name = "k_stage";
     else if (c->cfg.scheme == SWE_WAF) *name = "k_stage_tiled_waf";
-    else *name = learned ? "k_stage_tiled+k_limiter_phi" : "k_stage_tiled";
-    *launches_per_step = stages + (learned ? 1 : 0);
+    else *name = learned && !c->cfg.phi_in_stage ? "k_stage_tiled+k_limiter_phi" : "k_stage_tiled";
+    *launches_per_step = stages + (learned && (cell_kernel || !c->cfg.phi_in_stage) ? 1 : 0);
     return SWE_OK;
 }
 

@@ -3,12 +3,14 @@
 // ReLU, sigmoid) whose output phi in [0, 1] scales the central MUSCL slope
 // (U_R - U_Lupw)/|x_R - x_Lupw| of Sec. 6.2.3.
 //
-//  * Inference (k_limiter_phi): BF16 weights and activations on the matrix
-//    cores (v_mfma_f32_16x16x16bf16_1k), FP32 accumulation.  One thread per
-//    cell builds the features of its three half-edges into LDS; each wave
-//    then runs 12 tiles of 16 half-edges through the network (8 MFMAs per
-//    tile, all layers computed transposed so that each accumulator feeds
-//    the next layer directly, biases as the accumulators' initial values).
+//  * Inference (swe_mlp_dev.h): BF16 weights and activations on the matrix
+//    cores, FP32 accumulation, 64 half-edges per wave in four tiles of 16
+//    (five MFMAs per tile: two v_mfma_f32_16x16x16bf16_1k for the
+//    14-input layer, v_mfma_f32_16x16x32_bf16 for the hidden and the output
+//    layer).  k_limiter_phi evaluates every half-edge of the mesh ahead of
+//    a step (one thread per cell builds the features of its three
+//    half-edges); the tiled stage kernel can evaluate the same network
+//    inside its first phase instead (phi_in_stage).
 //  * Training data (k_restrict, k_pairs): the fine-mesh state restricted to
 //    the coarse mesh (mean of the four red-refinement children) gives the
 //    stencils; the target of a half-edge is the mean of the two children of
@@ -27,54 +29,13 @@
 #include "swe_ctx.h"
 #include "swe_internal.h"
 #include "swe_kernels.h"
+#include "swe_mlp_dev.h"
 
 using namespace swe;
-
-typedef short s4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 namespace {
 
 constexpr int kRec = 40;  // floats per training record
-
-// Inference weights: BF16 matrices (layer-1 K padded 14 -> 16 with zeros),
-// biases and the output layer as floats holding BF16-rounded values.
-struct MlpDev {
-    uint16_t W1[kMlpH * 16];
-    uint16_t W2[kMlpH * kMlpH];
-    float b1[kMlpH], b2[kMlpH], W3[kMlpH], b3, pad[3];
-};
-
-// round-to-nearest-even float -> bfloat16 bits (finite inputs)
-__host__ __device__ inline uint16_t bf16_bits(float f)
-{
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__host__ __device__ inline float bf16_float(uint16_t b)
-{
-    uint32_t u = (uint32_t)b << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-__device__ __forceinline__ float bf16_round(float f) { return bf16_float(bf16_bits(f)); }
-// the same rounding (to nearest, ties to even) by the hardware conversion
-__device__ __forceinline__ uint16_t bf16_bits_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
-__device__ __forceinline__ float bf16_round_hw(float f) { return (float)(__bf16)f; }
-// ReLU of an MFMA accumulator (4 values), rounded to BF16 and packed as the
-// B operand of the next MFMA (two values per conversion)
-__device__ __forceinline__ s4v relu_bf16x4(f4v d)
-{
-    const f2v lo = {fmaxf(d[0], 0.f), fmaxf(d[1], 0.f)}, hi = {fmaxf(d[2], 0.f), fmaxf(d[3], 0.f)};
-    const unsigned a = __builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf2v));
-    const unsigned b = __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf2v));
-    return __builtin_bit_cast(s4v, (unsigned long long)a | ((unsigned long long)b << 32));
-}
 
 __device__ __forceinline__ int xcd_tile_m(int bid, int nb)
 {
@@ -107,24 +68,11 @@ template <typename T> struct PhiArgs {
     T g, eps;
 };
 
-// Every LDS buffer of k_limiter_phi belongs to one wave, so its lanes
-// exchange data through LDS without a block barrier: the wave's LDS
-// operations are processed in order, and the compiler keeps the accesses to
-// the same buffers in program order; this waits for the wave's own
-// outstanding LDS operations and stops the compiler from moving LDS access
-// across it.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
 {
     using T4 = typename V4<T>::type;
-    __shared__ uint16_t X[4][192][16];
+    __shared__ __align__(16) uint16_t X[4][192][16];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c0 = xcd_tile_m(blockIdx.x, gridDim.x) * 256 + wv * 64;
     const int c = c0 + lane;
@@ -151,74 +99,20 @@ __global__ void __launch_bounds__(256) k_limiter_phi(PhiArgs<T> a)
             const T4 co = a.he_co[m * a.n + c];
             const bool ok = limiter_features<T, T4>(Uc, Um, hm, Ua, ha, Ub, hb, co.x, co.y, co.z,
                                                     co.w, a.g, a.eps, f);
-#pragma unroll
-            for (int i = 0; i < kMlpIn; ++i) X[wv][3 * lane + m][i] = bf16_bits_hw(f[i]);
-            // column 14 is padding; column 15 (zero weights) flags an eligible half-edge
-            X[wv][3 * lane + m][14] = 0;
-            X[wv][3 * lane + m][15] = ok ? 0x3F80 : 0;
+            mlp_write_row(X[wv][3 * lane + m], f, ok);
         }
     } else {
+        const float f0[kMlpIn] = {};
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-            for (int i = 0; i < 16; ++i) X[wv][3 * lane + m][i] = 0;
+        for (int m = 0; m < 3; ++m) mlp_write_row(X[wv][3 * lane + m], f0, false);
     }
-    // All three layers run transposed, units x half-edges: the weights are
-    // the A operand (lane: unit col (+16), inputs kq..kq+3 (+16)), the layer
-    // input the B operand (lane: half-edge col, inputs kq..kq+3) and the
-    // bias the accumulator's initial value (lane: units kq..kq+3), so a
-    // layer's accumulator (lane: units kq..kq+3 of half-edge col) is, after
-    // ReLU and BF16 rounding, the next layer's B operand as it stands.
-    const int col = lane & 15, kq = (lane >> 4) * 4;
-    const MlpDev *w = a.w;
-    s4v W1f[2], W2f[2][2], W3r[2];
-    f4v b1v[2], b2v[2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        W1f[nt] = *(const s4v *)&w->W1[(nt * 16 + col) * 16 + kq];
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) W2f[kb][nt] = *(const s4v *)&w->W2[(nt * 16 + col) * 32 + kb * 16 + kq];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            b1v[nt][j] = w->b1[nt * 16 + kq + j];
-            b2v[nt][j] = w->b2[nt * 16 + kq + j];
-            W3r[nt][j] = (short)bf16_bits_hw(w->W3[nt * 16 + kq + j]);
-        }
-    }
-    const s4v zero4 = {0, 0, 0, 0};
-    // b3 in element 0 of every lane: rows 0, 4, 8 and 12 of the accumulator
-    const f4v c3 = {w->b3, 0.f, 0.f, 0.f};
+    const MlpLane L = mlp_lane(a.w, lane);
     wave_lds_sync();
-    // Tiles in groups of four: the output layer of tile q holds W3 in row 4q
-    // of its A operand, so its 16 results are element 0 of lanes 16q..16q+15;
-    // one select per lane then gathers the four tiles, and the sigmoid and
-    // the store run once per group on all 64 lanes (half-edge rg * 64 + lane).
-    // Each tile keeps an accumulator of its own: a non-finite value in one
-    // tile cannot reach another's result.
+    // rows 3 l + m (cell l of the wave, local edge m) in three groups of 64
     for (int rg = 0; rg < 3; ++rg) {
-        f4v o[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rt = rg * 4 + q;
-            // B: features kq..kq+3 of half-edge rt * 16 + col
-            const s4v xb = *(const s4v *)&X[wv][rt * 16 + col][kq];
-            const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[0], xb, b1v[0], 0, 0, 0);
-            const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W1f[1], xb, b1v[1], 0, 0, 0);
-            const s4v h0 = relu_bf16x4(d0), h1 = relu_bf16x4(d1);
-            f4v e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][0], h0, b2v[0], 0, 0, 0);
-            e0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][0], h1, e0, 0, 0, 0);
-            f4v e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[0][1], h0, b2v[1], 0, 0, 0);
-            e1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W2f[1][1], h1, e1, 0, 0, 0);
-            const s4v g0 = relu_bf16x4(e0), g1 = relu_bf16x4(e1);
-            const bool mine = col == 4 * q;
-            o[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mine ? W3r[0] : zero4, g0, c3, 0, 0, 0);
-            o[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mine ? W3r[1] : zero4, g1, o[q], 0, 0, 0);
-        }
-        const int grp = lane >> 4;
-        const float z = grp == 0 ? o[0][0] : (grp == 1 ? o[1][0] : (grp == 2 ? o[2][0] : o[3][0]));
         const int row = rg * 64 + lane;
-        // NaN (not evaluated) where the half-edge is not reconstructed to
-        // second order: a stage that does reconstruct it falls back to minmod
-        const float ph = X[wv][row][15] ? 1.0f / (1.0f + expf(-z)) : __builtin_nanf("");
+        const float z = mlp_rows_z(L, X[wv] + rg * 64, lane);
+        const float ph = mlp_phi(z, X[wv][row][15] != 0);
         if (c0 + row / 3 < a.n) a.phi[3 * c0 + row] = ph;
     }
 }

@@ -92,6 +92,40 @@ def test_learned_limiter_steps(prec, tol):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("prec,integ,block,P", [(0, 1, 256, 1), (1, 1, 256, 1), (0, 0, 256, 1),
+                                                 (0, 1, 64, 1), (0, 1, 512, 1), (0, 1, 256, 4)])
+def test_network_in_stage_equals_separate_kernel(prec, integ, block, P):
+    """phi evaluated by the stand-alone network kernel ahead of each step (the
+    default) and inside the tiled kernel's first stage (the network on the
+    stage's own stencil, the far side of a tile-crossing edge evaluated where
+    it is needed) give bitwise the same states: RK2 and Euler, FP32 and
+    FP64, every tile size, and a sub-domain with ghost layers."""
+    sc = small_river()
+    h, hu, hv = flowing_state(sc)
+    sc.h, sc.hu, sc.hv = h, hu, hv
+    w = params(1)
+    swe, prepare_scenario = lib()
+    pr = prepare_scenario(sc, P=P, p=1 if P > 1 else 0, k=4 if P > 1 else 0)
+    dt = None
+    states = []
+    for pis in (0, 1):
+        s, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=prec, prepared=pr, limiter=3,
+                               integrator=integ, block=block, phi_in_stage=pis)
+        s.limiter_set_weights(w)
+        name, launches = s.step_kernel()
+        assert launches == (2 if integ else 1) + 1 - pis, (name, launches)
+        if dt is None:
+            l2g = pr.sub.l2g
+            M, _ = O.global_mesh(sc)
+            par = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2 if integ else O.EULER)
+            dt = 0.5 * M.dt(par, h, hu, hv)
+        s.step(40, dt)
+        states.append(s.read_state())
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+    assert np.all(np.isfinite(states[0][0]))
+
+
 def fine_pair(sc, steps=100):
     """Coarse and red-refined scenario, the fine one run by the oracle and
     loaded into a solver; returns solvers, prepared meshes, the children map
