@@ -244,7 +244,7 @@ def main():
         from paper_2307_16758_amd.limiter_train import init_params
         mlp = init_params()
         s.limiter_set_weights(mlp)
-    sendbuf = None
+    sendbuf = recvbuf = None
     if isinstance(sc, list):                      # batched ensemble
         preps = [prepare_scenario(x) for x in sc]
         s.mesh_upload_batch([p.mesh for p in preps])
@@ -273,8 +273,16 @@ def main():
         n_owned = pr.sub.n_owned
         name = sc.name
         if P > 1:
-            n_send, _ = s.ghost_sizes()
+            n_send, n_ghost = s.ghost_sizes()
             sendbuf = torch.empty(3 * max(1, n_send), dtype=torch.float32, device="cuda")
+            # the peers' values of each exchange: the ghosts' initial state
+            # stands in for them (no peer runs here), so the ghost layers
+            # stay a fixed boundary instead of stepping beyond the CFL limit
+            # of the owned cells
+            g = l2g[n_owned:]
+            recvbuf = torch.from_numpy(np.concatenate([sc.h[g], sc.hu[g], sc.hv[g]])
+                                       .astype(np.float32)).cuda()
+            torch.cuda.synchronize()
 
     tuned = s.autotune(10) if args.autotune else None
     s.step(args.warmup)
@@ -309,11 +317,13 @@ def main():
         elif args.overlap:
             for _ in range(nsteps):     # one step per exchange interval, pack overlapped
                 s.step_overlap(sendbuf)
+                s.unpack_ghosts(recvbuf)
             s.sync()
         else:
-            for _ in range(nsteps):     # one step per exchange interval + on-device pack
+            for _ in range(nsteps):     # one step per exchange interval: step, pack, unpack
                 s.step(1)
                 s.pack_ghosts(sendbuf)
+                s.unpack_ghosts(recvbuf)
             s.sync()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -366,7 +376,7 @@ def main():
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
                                f"{'MUSCL-HLLC-RK2' if rk2 else scheme_name + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
-                               + (f", part of {P} with {k} ghost layers + pack"
+                               + (f", part of {P} with {k} ghost layers + pack and unpack"
                                   + (" (high-overlap steps)" if args.overlap else "") if P > 1 else "")
                                + (f", snapshot to host every {args.snapshot_every} steps"
                                   if args.snapshot_every > 0 else ""),

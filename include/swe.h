@@ -51,8 +51,8 @@ extern "C" {
 #define SWE_ERR_ARG -1            /* bad argument (null pointer, bad size, bad enum) */
 #define SWE_ERR_MESH -2           /* mesh fails validation at upload */
 #define SWE_ERR_STATE -3          /* state missing or invalid (e.g. negative depth given) */
-#define SWE_ERR_NONFINITE -4      /* a NaN/Inf appeared in the state while stepping */
-#define SWE_ERR_NEGATIVE_DEPTH -5 /* a depth below -eps appeared while stepping */
+#define SWE_ERR_NONFINITE -4      /* a NaN/Inf appeared in an owned cell while stepping */
+#define SWE_ERR_NEGATIVE_DEPTH -5 /* a depth below -eps appeared in an owned cell while stepping */
 #define SWE_ERR_DEVICE -6         /* HIP runtime error */
 #define SWE_ERR_OOM -7            /* an allocation failed (device; host in the toolkit) */
 #define SWE_ERR_UNSUPPORTED -8    /* option not available in this build */
@@ -282,7 +282,9 @@ int swe_time(swe_ctx *ctx, double *t);      /* simulated time (syncs) */
  * anywhere (step 0, as one context would).  With cfl_rule 1 the global
  * step is not the minimum of the parts' steps. */
 int swe_local_dt(swe_ctx *ctx, double *dt);
-int swe_health(swe_ctx *ctx, int *bits);    /* SWE_HEALTH_* bits since the last set_state */
+int swe_health(swe_ctx *ctx, int *bits);    /* SWE_HEALTH_* bits since the last set_state,
+                                               over owned cells (a ghost cell's new state is
+                                               provisional: the next exchange replaces it) */
 
 /* Gather the owned cells listed in send_idx into dev_sendbuf, laid out
  * [3][n_send] (h, hu, hv; context precision), in CSR order of the peers.

@@ -329,6 +329,7 @@ template <typename T> struct StageArgs {
     // L / area; d_mid / d_central
     const T4 *he_co;
     const T *he_lam, *he_gam;
+    const T *he_dfw;  // tiled WAF: centroid distance d_fwd per half-edge (edge-major)
     const T4 *Uin, *U0;
     T4 *Uout;
     ClockWord *clock;
@@ -652,7 +653,9 @@ __device__ __forceinline__ CflVal<T> stage_cell(const StageArgs<T> &a, const int
         out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
         a.Uout[c] = out;
         pack_own(a, c, nh, nu, nv);
-        if (flags) atomicOr(a.health, flags);
+        // health counts owned cells: a ghost cell's new state is provisional
+        // (the next exchange replaces it)
+        if (flags && ((word >> kOwnedBit) & 1u)) atomicOr(a.health, flags);
         cfl.scen = s;
         if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
             const T u = fdiv(nu, nh), v = fdiv(nv, nh);
@@ -1095,7 +1098,9 @@ k_stage_tiled(StageArgs<T> a)
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
             stx(a.Uout, c, out);
             pack_own(a, c, nh, nu, nv);
-            if (flags) atomicOr(a.health, flags);
+            // health counts owned cells: a ghost cell's new state is provisional
+            // (the next exchange replaces it)
+            if (flags && ((word >> kOwnedBit) & 1u)) atomicOr(a.health, flags);
             cfl.scen = s;
             if (a.kind != 1 && ((word >> kOwnedBit) & 1u) && nh > eps) {
                 const T r = frcp(nh);
@@ -1134,7 +1139,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
     __shared__ unsigned char sH[3 * TILE];  // the half-edge has an upwind cell
     __shared__ unsigned sTask[3 * TILE];
     __shared__ int sK[3 * TILE];
-    __shared__ unsigned sW[TILE];
+    __shared__ T sRad[TILE];           // inscribed radius of each cell (positivity)
     __shared__ T sDt[TILE];
     __shared__ int sCount[2];
     __shared__ CflVal<T> sCfl[TILE / 64];
@@ -1152,11 +1157,14 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
         const DtPrefetch dtp = dt_prefetch(a.clock, a.ncopy, a.slot_cur,
                                            active ? (int)((unsigned)nb4.w >> kScenShift) : -1, a.dt_fixed);
         T4 Ukeep;
+        T man2 = T(0);
         const unsigned word = (unsigned)nb4.w;
         if (active) {
             const T4 Uc = ldx(a.Uin, c);
             Ukeep = Uc;
-            sW[cl] = word;
+            const T4 cg = ldx(a.cell, c);
+            sRad[cl] = cg.y;
+            man2 = cg.z;
             const bool hn0 = nb4.x >= 0, hn1 = nb4.y >= 0, hn2 = nb4.z >= 0;
             const T4 Un0 = a.Uin[hn0 ? nb4.x : c], Un1 = a.Uin[hn1 ? nb4.y : c], Un2 = a.Uin[hn2 ? nb4.z : c];
 #pragma unroll
@@ -1174,7 +1182,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
                 const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
                 const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
-                const T4 ge = a.he_geo[3 * c + m];
+                const T4 ge = ldx(a.he_co, m * a.n + c);  // unit normal in .x, .y
                 T4 rv;
                 rv.x = Uc.x;
                 rv.y = Uc.w;
@@ -1213,11 +1221,11 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
                 const int tc = c0 + tl;
                 const int k = inside ? c0 + kl : sK[m * TILE + tl];
-                const T4 ge = a.he_geo[3 * tc + m];
+                const T4 ge = ldx(a.he_co, m * a.n + tc);
                 const T nx = ge.x, ny = ge.y;
                 if (k < 0) {  // boundary flux (Sec. 6.1), printed form, global frame
                     const T4 Ut = ldx(a.Uin, tc);
-                    const int st = (int)(sW[tl] >> kScenShift);
+                    const int st = (int)((unsigned)ldx(a.nbr, tc).w >> kScenShift);
                     const ScenParams sp = a.scen[st];
                     const T q_in = k == kBcInflow
                                        ? T(inflow_at(sp, a.ser_t, a.ser_q,
@@ -1275,10 +1283,10 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 w.hasRu = isL ? kh : oh;
                 T F[3];
                 const T dtt = sDt[tl];
-                flux_waf<T, WAFM>(g, eps, fdiv(dtt, a.he_dist[3 * tc + m].w), UL, UR, w, F);
+                flux_waf<T, WAFM>(g, eps, fdiv(dtt, ldx(a.he_dfw, m * a.n + tc)), UL, UR, w, F);
                 if (a.waf_pos) {
-                    const T Ro = ((const T *)a.cell)[4 * (size_t)tc + 1];
-                    const T Rk = ((const T *)a.cell)[4 * (size_t)k + 1];
+                    const T Ro = sRad[tl];
+                    const T Rk = inside ? sRad[kl] : ((const T *)a.cell)[4 * (size_t)k + 1];
                     waf_positivity(g, eps, UL, UR, Lv.x, isL ? Ro : Rk, Rv.x, isL ? Rk : Ro, dtt, F);
                 }
                 const T sg = isL ? T(1) : T(-1);
@@ -1316,7 +1324,6 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
             T nh = Uc.x - dt * acc0;
             T nu = Uc.y - dt * acc1;
             T nv = Uc.z - dt * acc2;
-            const T4 cg = ldx(a.cell, c);
             int flags = 0;
             if (!(isfinite(nh) && isfinite(nu) && isfinite(nv))) flags |= kHealthNonfinite;
             if (nh < T(0)) {
@@ -1325,9 +1332,9 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
             }
             if (nh <= eps) {
                 nu = T(0); nv = T(0);
-            } else if (cg.z > T(0)) {  // Manning, point-implicit
+            } else if (man2 > T(0)) {  // Manning, point-implicit
                 const T sp = sqrt(nu * nu + nv * nv) * frcp(nh);
-                const T f = T(1) + dt * g * cg.z * sp * pow_m43(nh);
+                const T f = T(1) + dt * g * man2 * sp * pow_m43(nh);
                 const T rf = frcp(f);
                 nu *= rf; nv *= rf;
             }
@@ -1335,13 +1342,15 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
             out.x = nh; out.y = nu; out.z = nv; out.w = Uc.w;
             stx(a.Uout, c, out);
             pack_own(a, c, nh, nu, nv);
-            if (flags) atomicOr(a.health, flags);
+            // health counts owned cells: a ghost cell's new state is provisional
+            // (the next exchange replaces it)
+            if (flags && ((word >> kOwnedBit) & 1u)) atomicOr(a.health, flags);
             cfl.scen = s;
             if (((word >> kOwnedBit) & 1u) && nh > eps) {
                 const T r = frcp(nh);
                 const T u = nu * r, v = nv * r;
                 const T lm = sqrt(u * u + v * v) + sqrt(g * nh);
-                cfl = cfl_cell<T>(a.cfl_rule, s, cg.y, lm);
+                cfl = cfl_cell<T>(a.cfl_rule, s, sRad[cl], lm);
             }
         }
         cfl_commit(a.clock, a.ncopy, a.slot_next, a.cfl_rule, cfl, sCfl);
@@ -1469,7 +1478,7 @@ void release_mesh(swe_ctx *c)
 {
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
     dfree(c, c->nbr); dfree(c, c->cell); dfree(c, c->man2); dfree(c, c->he_geo); dfree(c, c->he_dist);
-    dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam);
+    dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam); dfree(c, c->he_dfw);
     dfree(c, c->U[0]); dfree(c, c->U[1]); dfree(c, c->U1); dfree(c, c->tmp3); dfree(c, c->bed);
     dfree_t(c, c->phi); dfree_t(c, c->clock); dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
     dfree_t(c, c->t0); dfree_t(c, c->send_idx); dfree_t(c, c->pk_off); dfree_t(c, c->pk_ent);
@@ -1517,7 +1526,11 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
     // edge length over the cell area
     // Stored edge-major (half-edge m of cell c at m * n + c), so that a
     // wave's loads of one local edge are contiguous.
-    std::vector<T> co(12 * n), lam(3 * n), gam(3 * n);
+    // The tiled WAF kernel takes the normal from the same set and the
+    // centroid distance of its Courant numbers from one more edge-major
+    // array (WAF contexts only).
+    const bool waf = c->cfg.scheme == SWE_WAF;
+    std::vector<T> co(12 * n), lam(3 * n), gam(3 * n), dfw(waf ? 3 * n : 0);
     for (size_t cc = 0; cc < n; ++cc)
         for (size_t m = 0; m < 3; ++m) {
             const size_t h = 3 * cc + m, e = m * n + cc;
@@ -1528,7 +1541,12 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
             co[4 * e + 3] = T(ge[3] * gd[1]);
             lam[e] = T(ge[2] * g.cell[4 * cc]);
             gam[e] = T(ge[3] * gd[2]);
+            if (waf) dfw[e] = T(gd[3]);
         }
+    if (waf) {
+        HIP_OK(c, dalloc(c, (void **)&c->he_dfw, 3 * sizeof(T) * n));
+        HIP_OK(c, hipMemcpy(c->he_dfw, dfw.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
+    }
     HIP_OK(c, dalloc(c, (void **)&c->he_co, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_co, co.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
     HIP_OK(c, dalloc(c, (void **)&c->he_lam, 3 * sizeof(T) * n));
@@ -1692,6 +1710,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     a.he_co = (const T4 *)c->he_co;
     a.he_lam = (const T *)c->he_lam;
     a.he_gam = (const T *)c->he_gam;
+    a.he_dfw = (const T *)c->he_dfw;
     a.clock = c->clock;
     a.ncopy = c->ncopy;
     a.scen = c->scen;

@@ -164,3 +164,44 @@ def test_borrowed_stream_orders_with_torch():
     ref = s2.read_state()
     for f in range(3):
         assert np.array_equal(b[f], ref[f][pr.sub.send_idx])
+
+
+@pytest.mark.parametrize("name,k", [("hllc1", 2), ("waf", 2), ("muscl_minmod_euler", 4)])
+def test_health_counts_owned_cells_only(name, k):
+    """A ghost cell's new state is provisional (the next exchange replaces
+    it), so a depth driven negative there raises no error; the same state in
+    an owned cell does.  Lake at rest, except that the outermost ghost layer
+    (or, as the control, as many owned cells) gets 20 m/s with a step far
+    beyond its CFL limit: one Euler step cannot carry that layer's state to
+    an owned cell, whose new states equal those of the unperturbed run
+    bitwise."""
+    swe, prepare_scenario = lib()
+    sc = wavy_scenario()
+    sc.h = np.maximum(1.2 - sc.b, 0.0)
+    sc.hu = np.zeros_like(sc.h)
+    sc.hv = np.zeros_like(sc.h)
+    pr = prepare_scenario(sc, P=3, p=1, k=k)
+    n_own = pr.sub.n_owned
+    outer = np.where((pr.sub.nbr == swe.BC_HALO).any(axis=1))[0]
+    assert outer.size > 0 and outer.min() >= n_own
+    inner = np.arange(n_own // 2, n_own // 2 + outer.size)
+    runs = {}
+    for where, cells in (("none", outer[:0]), ("ghost", outer), ("owned", inner)):
+        s, _, _, _ = make_pair(sc, name, precision=0, prepared=pr)
+        h, hu, hv = (x[pr.sub.l2g].copy() for x in (sc.h, sc.hu, sc.hv))
+        hu[cells] = 20.0 * h[cells]
+        hv[cells] = -20.0 * h[cells]
+        s.set_state(h, hu, hv)
+        if where == "owned":
+            with pytest.raises(swe.SweError):
+                s.step(1, 5.0)
+                s.sync()
+            continue
+        s.step(1, 5.0)
+        s.sync()
+        assert s.health() == 0, where
+        runs[where] = s.read_state()
+    for f in range(3):
+        assert np.array_equal(runs["ghost"][f][:n_own], runs["none"][f][:n_own])
+    g = runs["ghost"][0][outer]
+    assert np.any((g == 0) | ~np.isfinite(g))   # the layer was driven dry (clipped)
