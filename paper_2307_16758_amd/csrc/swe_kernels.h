@@ -354,22 +354,26 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
                                                  bool ha, const T4 &Ub, bool hb, T nx, T ny, T al,
                                                  T be, T g, T eps, float f[kMlpIn])
 {
+    // one test up front (a wave whose half-edges are all dry or one-sided
+    // skips the rest), then no divergent branch: the upwind state is a select
+    const bool ok = hk_ && Uc.x > eps && Uk.x > eps && (!ha || Ua.x > eps) && (!hb || Ub.x > eps) &&
+                    (ha || hb);
+    if (!ok) {
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) f[i] = 0.0f;
-    if (!hk_ || !(Uc.x > eps) || !(Uk.x > eps)) return false;
-    if ((ha && !(Ua.x > eps)) || (hb && !(Ub.x > eps)) || (!ha && !hb)) return false;
+        for (int i = 0; i < kMlpIn; ++i) f[i] = 0.0f;
+        return false;
+    }
     const T qc[4] = {Uc.x, Uc.y * nx + Uc.z * ny, -Uc.y * ny + Uc.z * nx, Uc.w};
     const T qk[4] = {Uk.x, Uk.y * nx + Uk.z * ny, -Uk.y * ny + Uk.z * nx, Uk.w};
+    // upwind state: the mean of the two upwind cells, or the one that exists
+    const bool both = ha && hb;
+    const T4 &Uo = ha ? Ua : Ub;
     T qu[4];
-    if (ha && hb) {
-        qu[0] = T(0.5) * (Ua.x + Ub.x);
-        qu[1] = T(0.5) * ((Ua.y * nx + Ua.z * ny) + (Ub.y * nx + Ub.z * ny));
-        qu[2] = T(0.5) * ((-Ua.y * ny + Ua.z * nx) + (-Ub.y * ny + Ub.z * nx));
-        qu[3] = T(0.5) * (Ua.w + Ub.w);
-    } else {
-        const T4 &Uo = ha ? Ua : Ub;
-        qu[0] = Uo.x; qu[1] = Uo.y * nx + Uo.z * ny; qu[2] = -Uo.y * ny + Uo.z * nx; qu[3] = Uo.w;
-    }
+    qu[0] = both ? T(0.5) * (Ua.x + Ub.x) : Uo.x;
+    qu[1] = both ? T(0.5) * ((Ua.y * nx + Ua.z * ny) + (Ub.y * nx + Ub.z * ny)) : Uo.y * nx + Uo.z * ny;
+    qu[2] = both ? T(0.5) * ((-Ua.y * ny + Ua.z * nx) + (-Ub.y * ny + Ub.z * nx))
+                 : -Uo.y * ny + Uo.z * nx;
+    qu[3] = both ? T(0.5) * (Ua.w + Ub.w) : Uo.w;
     const T hc = Uc.x;
     const T sh = hc + T(0.01), sq = hc * sqrt(g * hc) + T(0.01);
     const T sc[4] = {sh, sq, sq, sh};

@@ -138,8 +138,10 @@ __device__ __forceinline__ void mlp_write_row(uint16_t *row, const float f[kMlpI
 {
     unsigned u[8];
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
-        u[i] = (unsigned)bf16_bits_hw(f[2 * i]) | ((unsigned)bf16_bits_hw(f[2 * i + 1]) << 16);
+    for (int i = 0; i < 7; ++i) {  // two values per conversion (round to nearest even)
+        const f2v p = {f[2 * i], f[2 * i + 1]};
+        u[i] = __builtin_bit_cast(unsigned, __builtin_convertvector(p, bf2v));
+    }
     u[7] = ok ? 0x3F800000u : 0u;
     uint4 *r = (uint4 *)row;
     r[0] = make_uint4(u[0], u[1], u[2], u[3]);
