@@ -24,6 +24,7 @@ struct swe_ctx {
     void *nbr = nullptr, *cell = nullptr, *man2 = nullptr, *he_geo = nullptr, *he_dist = nullptr;
     void *he_co = nullptr, *he_lam = nullptr, *he_gam = nullptr;  // tiled kernel's half-edge set
     void *he_dfw = nullptr;     // tiled WAF kernel: centroid distance per half-edge (WAF contexts)
+    void *he_nrm = nullptr;     // tiled WAF kernel: unit normal per half-edge (WAF contexts)
     void *U[2] = {nullptr, nullptr}, *U1 = nullptr, *tmp3 = nullptr, *bed = nullptr;
     float *phi = nullptr;       // learned-limiter output, one per half-edge
     void *mlp = nullptr;        // learned-limiter weights (MlpDev, BF16)

@@ -330,6 +330,7 @@ template <typename T> struct StageArgs {
     const T4 *he_co;
     const T *he_lam, *he_gam;
     const T *he_dfw;  // tiled WAF: centroid distance d_fwd per half-edge (edge-major)
+    const typename V2<T>::type *he_nrm;  // tiled WAF: unit normal per half-edge (edge-major)
     const T4 *Uin, *U0;
     T4 *Uout;
     ClockWord *clock;
@@ -1182,7 +1183,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 const T4 Ub = mb == 0 ? Un0 : (mb == 1 ? Un1 : Un2);
                 const bool ha = ma == 0 ? hn0 : (ma == 1 ? hn1 : hn2);
                 const bool hb = mb == 0 ? hn0 : (mb == 1 ? hn1 : hn2);
-                const T4 ge = ldx(a.he_co, m * a.n + c);  // unit normal in .x, .y
+                const auto ge = ldx(a.he_nrm, m * a.n + c);  // unit normal
                 T4 rv;
                 rv.x = Uc.x;
                 rv.y = Uc.w;
@@ -1221,7 +1222,7 @@ __global__ void __launch_bounds__(TILE) k_stage_tiled_waf(StageArgs<T> a)
                 const int kl = inside ? (int)((task >> 15) & 1023u) : -1;
                 const int tc = c0 + tl;
                 const int k = inside ? c0 + kl : sK[m * TILE + tl];
-                const T4 ge = ldx(a.he_co, m * a.n + tc);
+                const auto ge = ldx(a.he_nrm, m * a.n + tc);
                 const T nx = ge.x, ny = ge.y;
                 if (k < 0) {  // boundary flux (Sec. 6.1), printed form, global frame
                     const T4 Ut = ldx(a.Uin, tc);
@@ -1478,7 +1479,7 @@ void release_mesh(swe_ctx *c)
 {
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
     dfree(c, c->nbr); dfree(c, c->cell); dfree(c, c->man2); dfree(c, c->he_geo); dfree(c, c->he_dist);
-    dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam); dfree(c, c->he_dfw);
+    dfree(c, c->he_co); dfree(c, c->he_lam); dfree(c, c->he_gam); dfree(c, c->he_dfw); dfree(c, c->he_nrm);
     dfree(c, c->U[0]); dfree(c, c->U[1]); dfree(c, c->U1); dfree(c, c->tmp3); dfree(c, c->bed);
     dfree_t(c, c->phi); dfree_t(c, c->clock); dfree_t(c, c->scen); dfree_t(c, c->ser_t); dfree_t(c, c->ser_q);
     dfree_t(c, c->t0); dfree_t(c, c->send_idx); dfree_t(c, c->pk_off); dfree_t(c, c->pk_ent);
@@ -1526,11 +1527,11 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
     // edge length over the cell area
     // Stored edge-major (half-edge m of cell c at m * n + c), so that a
     // wave's loads of one local edge are contiguous.
-    // The tiled WAF kernel takes the normal from the same set and the
-    // centroid distance of its Courant numbers from one more edge-major
-    // array (WAF contexts only).
+    // The tiled WAF kernel takes the unit normal and the centroid distance
+    // of its Courant numbers from two more edge-major arrays (WAF contexts
+    // only): it has no use for the MUSCL weights.
     const bool waf = c->cfg.scheme == SWE_WAF;
-    std::vector<T> co(12 * n), lam(3 * n), gam(3 * n), dfw(waf ? 3 * n : 0);
+    std::vector<T> co(12 * n), lam(3 * n), gam(3 * n), dfw(waf ? 3 * n : 0), nrm(waf ? 6 * n : 0);
     for (size_t cc = 0; cc < n; ++cc)
         for (size_t m = 0; m < 3; ++m) {
             const size_t h = 3 * cc + m, e = m * n + cc;
@@ -1541,11 +1542,17 @@ int upload_geometry(swe_ctx *c, const HostGeometry &g)
             co[4 * e + 3] = T(ge[3] * gd[1]);
             lam[e] = T(ge[2] * g.cell[4 * cc]);
             gam[e] = T(ge[3] * gd[2]);
-            if (waf) dfw[e] = T(gd[3]);
+            if (waf) {
+                dfw[e] = T(gd[3]);
+                nrm[2 * e] = T(ge[0]);
+                nrm[2 * e + 1] = T(ge[1]);
+            }
         }
     if (waf) {
         HIP_OK(c, dalloc(c, (void **)&c->he_dfw, 3 * sizeof(T) * n));
         HIP_OK(c, hipMemcpy(c->he_dfw, dfw.data(), 3 * sizeof(T) * n, hipMemcpyHostToDevice));
+        HIP_OK(c, dalloc(c, (void **)&c->he_nrm, 6 * sizeof(T) * n));
+        HIP_OK(c, hipMemcpy(c->he_nrm, nrm.data(), 6 * sizeof(T) * n, hipMemcpyHostToDevice));
     }
     HIP_OK(c, dalloc(c, (void **)&c->he_co, 12 * sizeof(T) * n));
     HIP_OK(c, hipMemcpy(c->he_co, co.data(), 12 * sizeof(T) * n, hipMemcpyHostToDevice));
@@ -1711,6 +1718,7 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     a.he_lam = (const T *)c->he_lam;
     a.he_gam = (const T *)c->he_gam;
     a.he_dfw = (const T *)c->he_dfw;
+    a.he_nrm = (const typename V2<T>::type *)c->he_nrm;
     a.clock = c->clock;
     a.ncopy = c->ncopy;
     a.scen = c->scen;

@@ -12,6 +12,9 @@ namespace swe {
 template <typename T> struct V4;
 template <> struct V4<float> { using type = float4; };
 template <> struct V4<double> { using type = double4; };
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
 
 enum { kHLLC1 = 0, kMUSCL = 1, kWAF = 2 };
 enum { kMinmod = 0, kSuperbee = 1, kVanAlbada = 2, kLearned = 3, kZeroSlope = 4 };
