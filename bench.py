@@ -147,10 +147,10 @@ def host_cpu():
     return model, os.cpu_count(), avail
 
 
-def cpu_baseline(sc, kw, seconds, mlp=None):
-    """Serial FP64 oracle on the same mesh (its own neighbour search, in
-    the generator's numbering): as many steps as fit in about ``seconds``
-    (at least one), one thread."""
+def _oracle_rate(sc, kw, seconds, mlp=None):
+    """(cell-updates, steps, seconds) of the serial FP64 oracle on one
+    scenario (its own neighbour search, in the generator's numbering): as
+    many steps as fit in about ``seconds`` (at least one)."""
     from oracle import oracle as O
     M, _ = O.global_mesh(sc)
     p = O.scenario_params(sc, scheme=kw["scheme"], integrator=kw["integrator"],
@@ -165,10 +165,55 @@ def cpu_baseline(sc, kw, seconds, mlp=None):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    return sc.n_cells * steps, steps, el
+
+
+def _member_rate(args):
+    """Worker of the aggregate baseline: ensemble member s on its own core."""
+    s, kw, seconds, cpu = args
+    if cpu is not None:
+        os.sched_setaffinity(0, {cpu})
+    from swe_inputs.scenarios import ensemble_member
+    sc = ensemble_member(s)
+    upd, steps, el = _oracle_rate(sc, kw, seconds)
+    return sc.n_cells, steps, upd / el
+
+
+def cpu_baseline(sc, kw, seconds, mlp=None):
+    """Serial FP64 oracle on the same mesh, pinned to one core of this
+    process's CPU set."""
+    cpus = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    if cpus:
+        os.sched_setaffinity(0, {cpus[0]})
+    try:
+        upd, steps, el = _oracle_rate(sc, kw, seconds, mlp)
+    finally:
+        if cpus:
+            os.sched_setaffinity(0, set(cpus))
     model, ncpu, avail = host_cpu()
-    return dict(value=sc.n_cells * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+    return dict(value=upd / el, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=f"{sc.name}: {sc.n_cells} cells, first {steps} steps, serial FP64 "
-                       f"({el:.1f} s)",
+                       f"({el:.1f} s, one core)",
+                host_cpu=model, nproc=ncpu, cores_available=avail)
+
+
+def cpu_baseline_aggregate(n_members, kw, seconds, max_workers=16):
+    """The ensemble's fair CPU comparison: independent serial FP64 oracle
+    processes, one per core (at most ``max_workers``), each stepping its own
+    member for about ``seconds``; the aggregate is the sum of their rates."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    cpus = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    w = max(1, min(max_workers, len(cpus) if cpus else (os.cpu_count() or 1), n_members))
+    jobs = [(s, kw, seconds, cpus[s] if cpus else None) for s in range(w)]
+    with ProcessPoolExecutor(max_workers=w, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_member_rate, jobs))
+    model, ncpu, avail = host_cpu()
+    cells = sum(r[0] for r in res)
+    return dict(value=sum(r[2] for r in res), unit="cell-updates/s", cores=w, kind="oracle",
+                sample=f"members 0-{w - 1} of the ensemble ({cells} cells), one serial FP64 "
+                       f"oracle process per core, each about {seconds:.0f} s "
+                       f"({min(r[1] for r in res)}-{max(r[1] for r in res)} steps)",
                 host_cpu=model, nproc=ncpu, cores_available=avail)
 
 
@@ -395,8 +440,10 @@ def main():
         "host": {"cpu": model, "nproc": ncpu, "cores_available": avail},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc[0] if isinstance(sc, list) else sc, kw,
-                                           args.cpu_seconds, mlp)
+        if isinstance(sc, list):    # the ensemble: one oracle process per core
+            out["cpu_baseline"] = cpu_baseline_aggregate(len(sc), kw, args.cpu_seconds)
+        else:
+            out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds, mlp)
     print(json.dumps(out), flush=True)
 
 

@@ -251,27 +251,30 @@ def config3(nx=5702, ny=1140) -> Scenario:
     return river_dam_break(nx=nx, ny=ny, seed=3)
 
 
+def ensemble_member(s, seed_base=5000, min_cells=5.0e4, max_cells=2.0e6, size_scale=1.0):
+    """Scenario s of the seeded flood ensemble (its own random stream, so
+    any member can be built alone)."""
+    seed = seed_base + s
+    rng = np.random.default_rng([seed, 303])
+    N = math.exp(rng.uniform(math.log(min_cells), math.log(max_cells)))
+    N *= size_scale
+    ny = max(2, int(round(math.sqrt(N / 10.0))))
+    nx = 5 * ny
+    q_peak = rng.uniform(100.0, 2000.0)
+    t_peak = rng.uniform(30.0, 90.0)
+    width = rng.uniform(0.2, 0.9) * t_peak      # rise starts after t = 0
+    manning = rng.uniform(0.02, 0.05)
+    hyd = (np.array([0.0, t_peak - width, t_peak, t_peak + width, 1.0e9]),
+           np.array([100.0, 100.0, q_peak, 100.0, 100.0]))
+    sc = river_channel(nx=nx, ny=ny, seed=seed, manning=manning,
+                       inflow_q=100.0, hydrograph=hyd,
+                       name=f"ensemble_{s:02d}")
+    sc.params.update(q_peak=q_peak, t_peak=t_peak, width=width)
+    return sc
+
+
 def ensemble_scenarios(n=64, seed_base=5000, min_cells=5.0e4, max_cells=2.0e6,
                        size_scale=1.0):
     """Seeded flood ensemble on the 10 km x 2 km channel.  ``size_scale``
     shrinks every mesh (for quick tests); 1.0 is the full recipe."""
-    out = []
-    for s in range(n):
-        seed = seed_base + s
-        rng = np.random.default_rng([seed, 303])
-        N = math.exp(rng.uniform(math.log(min_cells), math.log(max_cells)))
-        N *= size_scale
-        ny = max(2, int(round(math.sqrt(N / 10.0))))
-        nx = 5 * ny
-        q_peak = rng.uniform(100.0, 2000.0)
-        t_peak = rng.uniform(30.0, 90.0)
-        width = rng.uniform(0.2, 0.9) * t_peak      # rise starts after t = 0
-        manning = rng.uniform(0.02, 0.05)
-        hyd = (np.array([0.0, t_peak - width, t_peak, t_peak + width, 1.0e9]),
-               np.array([100.0, 100.0, q_peak, 100.0, 100.0]))
-        sc = river_channel(nx=nx, ny=ny, seed=seed, manning=manning,
-                           inflow_q=100.0, hydrograph=hyd,
-                           name=f"ensemble_{s:02d}")
-        sc.params.update(q_peak=q_peak, t_peak=t_peak, width=width)
-        out.append(sc)
-    return out
+    return [ensemble_member(s, seed_base, min_cells, max_cells, size_scale) for s in range(n)]
