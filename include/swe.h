@@ -118,7 +118,9 @@ typedef struct {
     int waves;         /* FP32 tiled kernel with 256-cell tiles (first-order HLLC and MUSCL
                           with a classic limiter): waves per SIMD it is built for, 6 or 7;
                           0 (default): 7 when that lets the chip hold every tile of a mesh
-                          of up to two rounds at once, else 6.  Same results either way. */
+                          of up to two rounds at once, or when a launch spans 8 or more
+                          rounds (then a persistent grid of 7 blocks per compute unit),
+                          else 6.  Same results either way. */
     int reserved0;
     /* Optional allocator of the context's device buffers (both NULL: hipMalloc
      * and hipFree), e.g. a framework's caching allocator.  alloc(bytes, user)

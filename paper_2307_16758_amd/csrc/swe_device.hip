@@ -1623,8 +1623,10 @@ template <typename T, int TILE, int OCC = SWE_TILED_WAVES> KernelFn<T> pick_tile
 // 256-cell tiles: each tile takes longer (72 registers instead of 80), but
 // the chip holds 7 instead of 6 tiles per compute unit.  Worth it when that
 // saves a round of tiles in a launch of at most two rounds (a sub-domain of
-// about 400k cells: one round instead of two); on larger meshes the two
-// are even, on config-2-sized ones six is faster.
+// about 400k cells: one round instead of two), and on a launch of many
+// rounds (8 or more), which then runs as a persistent grid of 7 blocks per
+// compute unit (measured 6% faster on the 13M-cell river); on
+// config-2-sized meshes (a few rounds) six is faster.
 template <typename T> bool seven_waves(const swe_ctx *c, int B)
 {
     if (sizeof(T) != 4 || B != 256 || c->cfg.scheme == SWE_WAF || c->cfg.cell_kernel ||
@@ -1634,6 +1636,7 @@ template <typename T> bool seven_waves(const swe_ctx *c, int B)
     const long long nt = (c->n_total + B - 1) / B, s6 = 6LL * c->ncu, s7 = 7LL * c->ncu;
     if (s6 <= 0) return false;
     const long long r6 = (nt + s6 - 1) / s6, r7 = (nt + s7 - 1) / s7;
+    if (r6 >= 8 && c->grid_persist >= 0) return true;  // persistent grid (see stage_grid)
     return r7 < r6 && r6 <= 2;
 }
 
