@@ -420,3 +420,34 @@ def test_outflow_steady_uniform_stream(name, kw):
     assert np.abs(h - h_ex).max() <= 1e-9, np.abs(h - h_ex).max()
     assert np.abs(hu - q).max() <= 1e-9, np.abs(hu - q).max()
     assert np.abs(hv).max() <= 1e-9
+
+
+def test_learned_limiter_rotational_invariance():
+    """The learned limiter's inputs are taken in each edge's own frame
+    (normal and tangential discharges, increments to the edge midpoint), so
+    rotating the mesh and the momentum rotates the solution: an input that
+    leaks a global-frame quantity (a Cartesian discharge, an unrotated
+    velocity) breaks this.  (The inputs
+    are not reflection-invariant: the tangential increments change sign in
+    a mirror image, so the network, unlike the classic limiters, need not
+    give mirror-symmetric results.)"""
+    sc = strip_riemann(L=10.0, W=2.0, nx=30, ny=6, hL=1.2, hR=0.6, uL=0.3, uR=-0.2,
+                       ends=BC_WALL)
+    sc.hv = sc.h * 0.1
+    th = 0.7
+    M0, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED)
+    p.mlp = np.random.default_rng(5).normal(0.0, 0.5, O.MLP_NPAR)
+    h0, hu0, hv0, _, _ = M0.run(p, sc.h, sc.hu, sc.hv, 60, dt_fixed=0.01)
+    # the network is not a constant here: its phi spans a good part of [0, 1]
+    inp, phi = O.limiter_inputs(M0, p, h0, hu0, hv0)
+    elig = inp[..., 23] == 1.0
+    assert elig.sum() > 100 and np.ptp(phi[elig]) > 0.2
+    xy = rotate_xy(sc.mesh.xy, th)
+    c, s = math.cos(th), math.sin(th)
+    M1 = O.Mesh(xy, sc.mesh.tri, M0.nbr, sc.b, sc.manning)
+    h1, hu1, hv1, _, _ = M1.run(p, sc.h, c * sc.hu - s * sc.hv, s * sc.hu + c * sc.hv, 60,
+                                dt_fixed=0.01)
+    np.testing.assert_allclose(h1, h0, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(hu1, c * hu0 - s * hv0, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(hv1, s * hu0 + c * hv0, rtol=0, atol=1e-10)
