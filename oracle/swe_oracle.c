@@ -494,9 +494,9 @@ double or_mlp_loss_grad(const double *params, int n, const double *x, const doub
  * Features of one half-edge for the learned limiter.  For each of h, q_n, q_t
  * (discharges in the edge frame) and b: tanh of the upwind and cross-edge
  * increments over the distance to the edge midpoint (slope times d_mid)
- * made dimensionless with the variable's scale, and the clipped ratio of
- * the two increments; then the cell Froude number and the relative depth
- * jump.
+ * made dimensionless with the variable's scale (for q_t, whose sign flips
+ * in a mirror image, their magnitudes), and the clipped ratio of the two
+ * increments; then the cell Froude number and the relative depth jump.
  * scale: h and b -> h_c + 0.01 m; q_n, q_t -> h_c * sqrt(g h_c) + 0.01 m^2/s.
  * ---------------------------------------------------------------------- */
 static void halfedge_features(double g, const double qc[4], const double qu[4],
@@ -509,8 +509,11 @@ static void halfedge_features(double g, const double qc[4], const double qu[4],
         /* the upwind and cross-edge increments over the distance to the edge
          * midpoint: slope times d_mid */
         double ab = (qc[k] - qu[k]) / du * dm, af = (qf[k] - qc[k]) / df * dm;
-        f[3 * k + 0] = tanh(ab / sc[k]);
-        f[3 * k + 1] = tanh(af / sc[k]);
+        /* q_t changes sign in a mirror image: its two increments enter by
+         * magnitude (their ratio keeps the relative sign), so that the
+         * features of mirror-image half-edges are equal */
+        f[3 * k + 0] = tanh((k == 2 ? fabs(ab) : ab) / sc[k]);
+        f[3 * k + 1] = tanh((k == 2 ? fabs(af) : af) / sc[k]);
         double r = ab * af / (af * af + 1e-12);
         f[3 * k + 2] = dmax(-2.0, dmin(2.0, r));
     }

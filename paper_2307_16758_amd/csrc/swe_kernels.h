@@ -346,7 +346,9 @@ constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlp
 // edge m (a design of this library; the paper has no learned limiter): for
 // h, q_n, q_t (discharges in the edge frame) and b, the upwind and
 // cross-edge increments to the edge midpoint ab = sb d_mid and af = sf d_mid
-// as tanh(a / scale) and their ratio ab af / (af^2 + 1e-12) clipped to
+// as tanh(a / scale) (for q_t, whose sign flips in a mirror image, of |a|:
+// the features of mirror-image half-edges are equal) and their ratio
+// ab af / (af^2 + 1e-12) clipped to
 // [-2, 2]; then tanh of the cell's Froude
 // number and of the relative depth jump across the edge.  Scales: h, b:
 // h_c + 0.01 m; q: h_c sqrt(g h_c) + 0.01 m^2/s.  Returns false when the
@@ -387,8 +389,10 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
         // and be = d_mid / d_fwd times the differences
         const T ab = al * (qc[k] - qu[k]), af = be * (qk[k] - qc[k]);
         const T isc = frcp(sc[k]);
-        f[3 * k + 0] = float(ftanh(ab * isc));
-        f[3 * k + 1] = float(ftanh(af * isc));
+        // q_t changes sign in a mirror image: its increments enter by
+        // magnitude (the ratio keeps their relative sign)
+        f[3 * k + 0] = float(ftanh((k == 2 ? fabs(ab) : ab) * isc));
+        f[3 * k + 1] = float(ftanh((k == 2 ? fabs(af) : af) * isc));
         const T r = fdiv(ab * af, af * af + T(1e-12));
         f[3 * k + 2] = float(tmin(T(2), tmax(T(-2), r)));
     }
