@@ -496,7 +496,8 @@ double or_mlp_loss_grad(const double *params, int n, const double *x, const doub
  * increments over the distance to the edge midpoint (slope times d_mid)
  * made dimensionless with the variable's scale (for q_t, whose sign flips
  * in a mirror image, their magnitudes), and the clipped ratio of the two
- * increments; then the cell Froude number and the relative depth jump.
+ * increments (regularized at 1% of the scale); then the cell Froude number
+ * and the relative depth jump.
  * scale: h and b -> h_c + 0.01 m; q_n, q_t -> h_c * sqrt(g h_c) + 0.01 m^2/s.
  * ---------------------------------------------------------------------- */
 static void halfedge_features(double g, const double qc[4], const double qu[4],
@@ -514,7 +515,9 @@ static void halfedge_features(double g, const double qc[4], const double qu[4],
          * features of mirror-image half-edges are equal */
         f[3 * k + 0] = tanh((k == 2 ? fabs(ab) : ab) / sc[k]);
         f[3 * k + 1] = tanh((k == 2 ? fabs(af) : af) / sc[k]);
-        double r = ab * af / (af * af + 1e-12);
+        /* the ratio of the two increments, regularized at 1% of the
+         * variable's scale: smooth where the forward increment vanishes */
+        double r = ab * af / (af * af + 1e-4 * sc[k] * sc[k]);
         f[3 * k + 2] = dmax(-2.0, dmin(2.0, r));
     }
     f[12] = tanh(sqrt(uc * uc + vc * vc) / sqrt(g * dmax(hc, 1e-6)));

@@ -348,7 +348,7 @@ constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlp
 // cross-edge increments to the edge midpoint ab = sb d_mid and af = sf d_mid
 // as tanh(a / scale) (for q_t, whose sign flips in a mirror image, of |a|:
 // the features of mirror-image half-edges are equal) and their ratio
-// ab af / (af^2 + 1e-12) clipped to
+// ab af / (af^2 + (0.01 scale)^2) clipped to
 // [-2, 2]; then tanh of the cell's Froude
 // number and of the relative depth jump across the edge.  Scales: h, b:
 // h_c + 0.01 m; q: h_c sqrt(g h_c) + 0.01 m^2/s.  Returns false when the
@@ -393,7 +393,8 @@ __device__ __forceinline__ bool limiter_features(const T4 &Uc, const T4 &Uk, boo
         // magnitude (the ratio keeps their relative sign)
         f[3 * k + 0] = float(ftanh((k == 2 ? fabs(ab) : ab) * isc));
         f[3 * k + 1] = float(ftanh((k == 2 ? fabs(af) : af) * isc));
-        const T r = fdiv(ab * af, af * af + T(1e-12));
+        // regularized at 1% of the scale: smooth where af vanishes
+        const T r = fdiv(ab * af, af * af + T(1e-4) * sc[k] * sc[k]);
         f[3 * k + 2] = float(tmin(T(2), tmax(T(-2), r)));
     }
     const T ih = frcp(hc);
