@@ -240,6 +240,9 @@ def main():
     ap.add_argument("--phi-in-stage", type=int, default=0,
                     help="learned limiter: 1 evaluates the network inside the first stage "
                          "instead of in a kernel of its own ahead of each step")
+    ap.add_argument("--phi-every", type=int, default=1, choices=(1, 2, 3, 6),
+                    help="learned limiter: evaluate the network every PHI_EVERY steps (the "
+                         "steps between reuse its last phi)")
     ap.add_argument("--snapshot-every", type=int, default=0, metavar="M",
                     help="take the state to pinned host memory every M steps (swe_snapshot, "
                          "copied on a side stream while the steps go on), inside the timed region")
@@ -283,7 +286,7 @@ def main():
     if args.limiter == "learned":
         kw = dict(kw, limiter=swe.LEARNED)
     s = swe.Solver(device=0, block=args.block, cell_kernel=args.cell_kernel,
-                   phi_in_stage=args.phi_in_stage, **kw)
+                   phi_in_stage=args.phi_in_stage, phi_every=args.phi_every, **kw)
     mlp = None
     if args.limiter == "learned":
         from paper_2307_16758_amd.limiter_train import init_params
@@ -339,6 +342,9 @@ def main():
     s.prepare()           # the step graph is captured here, outside every timed region
     s.sync()
     kname, launches_per_step = s.step_kernel()
+    if "k_limiter_phi" in kname and args.phi_every > 1:
+        # the network's launch runs on one step in phi_every
+        launches_per_step -= 1.0 - 1.0 / args.phi_every
     plain = sendbuf is None and args.snapshot_every <= 0
 
     def one_run(nsteps):
@@ -421,6 +427,8 @@ def main():
         "config": {"workload": f"{args.workload}: {name}, {n_owned} owned triangles, "
                                f"{'MUSCL-HLLC-RK2' if rk2 else scheme_name + '-Euler'}"
                                + (", learned limiter" if args.limiter == "learned" else "")
+                               + (f" (network every {args.phi_every} steps)"
+                                  if args.limiter == "learned" and args.phi_every > 1 else "")
                                + (f", part of {P} with {k} ghost layers + pack and unpack"
                                   + (" (high-overlap steps)" if args.overlap else "") if P > 1 else "")
                                + (f", snapshot to host every {args.snapshot_every} steps"

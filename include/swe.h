@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 4
+#define SWE_ABI_VERSION 5
 
 /* status codes */
 #define SWE_OK 0
@@ -121,7 +121,11 @@ typedef struct {
                           of up to two rounds at once, or when a launch spans 8 or more
                           rounds (then a persistent grid of 7 blocks per compute unit),
                           else 6.  Same results either way. */
-    int reserved0;
+    int phi_every;     /* SWE_LEARNED: phi is evaluated on the steps whose index since the
+                          last set_state is a multiple of phi_every (1, 2, 3 or 6; 0: every
+                          step), and on the first step after swe_limiter_set_weights or
+                          swe_autotune; the steps between reuse the last phi.  Each
+                          evaluation reads U^n of its own step, as with phi_every 1. */
     /* Optional allocator of the context's device buffers (both NULL: hipMalloc
      * and hipFree), e.g. a framework's caching allocator.  alloc(bytes, user)
      * returns memory on `device` usable by the context's stream, or NULL (the
@@ -271,7 +275,9 @@ int swe_prepare(swe_ctx *ctx, double dt_fixed);
 /* The kernel(s) one step launches under the context's configuration: *name
  * points to a static string (kernel names joined by '+'), and
  * *launches_per_step counts the launches of one step (e.g. 2 for the two
- * stage launches of RK2).  For measurement tools. */
+ * stage launches of RK2; a learned-limiter step that evaluates phi, where
+ * phi_every > 1 skips the network's launch on the steps between).  For
+ * measurement tools. */
 int swe_step_kernel(const swe_ctx *ctx, const char **name, int *launches_per_step);
 
 int swe_sync(swe_ctx *ctx);                 /* wait + report health */
@@ -312,8 +318,8 @@ int swe_last_step_ms(swe_ctx *ctx, float *ms);
  * Sec. 6.2.3.  It falls back to the minmod slope when phi is outside [0,1]
  * or NaN or the reconstructed depth is negative, and to first order where
  * the classic limiter does (dry stencil cell, boundary edge).  phi is
- * evaluated once per time step, from the state the step starts from, and
- * both RK2 stages use it.  Parameters
+ * evaluated once per time step (or every phi_every steps, see swe_config),
+ * from the state the step starts from, and both RK2 stages use it.  Parameters
  * are 1569 floats: W1[32][14], b1[32], W2[32][32], b2[32], W3[32], b3. */
 #define SWE_MLP_NPARAM 1569
 #define SWE_PAIR_RECORD 40  /* floats per training record */
@@ -322,7 +328,8 @@ int swe_last_step_ms(swe_ctx *ctx, float *ms);
 int swe_limiter_set_weights(swe_ctx *ctx, const float *params);
 /* phi of every half-edge of the current state into dev_phi[3*n_total]
  * (NaN where the half-edge is not reconstructed to second order: not
- * evaluated). */
+ * evaluated).  The phi that later steps reuse (phi_every > 1) is left as
+ * it was. */
 int swe_limiter_phi(swe_ctx *ctx, float *dev_phi);
 /* Training records from a fine solution on the red refinement of the coarse
  * mesh (both contexts on one device, same precision).  dev_children

@@ -47,7 +47,7 @@ class _Params(C.Structure):
                 ("inflow_len", C.c_double), ("outflow_stage", C.c_double),
                 ("n_series", C.c_int), ("pad", C.c_int),
                 ("series_t", C.POINTER(C.c_double)), ("series_q", C.POINTER(C.c_double)),
-                ("mlp", C.POINTER(C.c_double)), ("waf_pos", C.c_int), ("pad2", C.c_int)]
+                ("mlp", C.POINTER(C.c_double)), ("waf_pos", C.c_int), ("phi_every", C.c_int)]
 
 
 class _Sub(C.Structure):
@@ -117,6 +117,7 @@ class Params:
     limiter: int = MINMOD
     waf_limiter: int = WAF_SUPERBEE
     waf_pos: int = 1
+    phi_every: int = 1
     cfl_rule: int = 0
     mlp_bf16: int = 0
     inflow_q: float = 0.0
@@ -131,6 +132,7 @@ class Params:
                     self.limiter, self.waf_limiter, self.cfl_rule, self.mlp_bf16,
                     self.inflow_q, self.inflow_len, self.outflow_stage, 0, 0)
         p.waf_pos = self.waf_pos
+        p.phi_every = self.phi_every
         self._keep = []
         if self.hydrograph is not None:
             t = np.ascontiguousarray(self.hydrograph[0], np.float64)

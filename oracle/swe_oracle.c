@@ -45,7 +45,8 @@ typedef struct {
     const double *series_t, *series_q;
     const double *mlp; /* MLP_NPAR weights, layout of mlp_unpack() */
     int waf_pos;       /* WAF: 1 = mass flux kept within each donor cell's share (below) */
-    int pad2;
+    int phi_every;     /* learned limiter: phi evaluated on steps 0, k, 2k, ... of a run
+                          (the steps between keep the last phi); 0 or 1: every step */
 } or_params;
 
 typedef struct {
@@ -942,7 +943,7 @@ int or_run(or_mesh *M, const or_params *P, double *h, double *hu, double *hv, in
         double dt;
         if (dt_fixed > 0.0) dt = dt_fixed;
         else if (or_dt(M, P, h, hu, hv, &dt) != 0) return -1;
-        step_phi(M, P, h, hu, hv);
+        if (P->phi_every <= 1 || s % P->phi_every == 0) step_phi(M, P, h, hu, hv);
         if (P->integrator == OR_RK2) {
             stage(M, P, h, hu, hv, dt, *t, M->u0h, M->u0u, M->u0v, flags);
             stage(M, P, M->u0h, M->u0u, M->u0v, dt, *t + dt, M->u1h, M->u1u, M->u1v, flags);

@@ -29,6 +29,7 @@ struct swe_ctx {
     float *phi = nullptr;       // learned-limiter output, one per half-edge
     void *mlp = nullptr;        // learned-limiter weights (MlpDev, BF16)
     bool has_mlp = false;
+    bool phi_stale = false;  // learned limiter: the next step evaluates phi whatever its index
     unsigned long long *clock = nullptr;  // 3 slots x (1 + ncopy) lines per scenario
     int ncopy = 64;
     swe::ScenParams *scen = nullptr;
@@ -58,8 +59,8 @@ struct swe_ctx {
 
 namespace swe {
 // Learned limiter (swe_mlp.hip): phi of every half-edge of state U into
-// ctx->phi, on the context stream.
-int launch_limiter_phi(swe_ctx *c, const void *U);
+// out[3 * n_total], on the context stream.
+int launch_limiter_phi(swe_ctx *c, const void *U, float *out);
 // Clock slots of a freshly set state U[0] (time t, CFL minima); syncs.
 int init_clock(swe_ctx *c, double t);
 }  // namespace swe

@@ -1717,7 +1717,8 @@ struct OverlapPlan {
 };
 
 template <typename T>
-int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &ov = OverlapPlan())
+int launch_step(swe_ctx *c, long long step, double dt_fixed, bool phi_force = false,
+                const OverlapPlan &ov = OverlapPlan())
 {
     using T4 = typename V4<T>::type;
     StageArgs<T> a{};
@@ -1764,16 +1765,21 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     dim3 grid(cell_kernel ? ntiles : stage_grid(c, (const void *)k, B, ntiles));
     const dim3 blk(B);
     T4 *Ucur = (T4 *)c->U[step & 1];
-    // the learned limiter's phi is evaluated once per step, from U^n: by a
-    // kernel of its own ahead of the step, or (when the configuration asks
-    // for it, tiled kernel only) by the step's first stage
+    // the learned limiter's phi is evaluated from U^n of the steps whose
+    // index is a multiple of phi_every (every step by default; a step between
+    // reuses the stored phi): by a kernel of its own ahead of the step, or
+    // (when the configuration asks for it, tiled kernel only) by the step's
+    // first stage.  phi_every divides the graph's period, so a captured
+    // chunk, whose first step is aligned to it, evaluates on the same steps.
     const bool learned = c->cfg.scheme == SWE_MUSCL && c->cfg.limiter == SWE_LEARNED;
-    const bool phi_sep = learned && (cell_kernel || !c->cfg.phi_in_stage);
+    const long long pe = c->cfg.phi_every > 1 ? c->cfg.phi_every : 1;
+    const bool phi_now = learned && (phi_force || step % pe == 0);
+    const bool phi_sep = phi_now && (cell_kernel || !c->cfg.phi_in_stage);
     a.mlp = (const MlpDev *)c->mlp;
-    if (phi_sep && launch_limiter_phi(c, Ucur) != SWE_OK) return SWE_ERR_DEVICE;
+    if (phi_sep && launch_limiter_phi(c, Ucur, c->phi) != SWE_OK) return SWE_ERR_DEVICE;
     KernelFn<T> k1 = k;  // the step's first stage
     dim3 grid1 = grid;
-    if (learned && !phi_sep) {
+    if (phi_now && !phi_sep) {
         k1 = pick_kernel<T>(c->cfg.scheme, kLearnedNet, c->cfg.waf_limiter, B, 0, false, euler);
         grid1 = dim3(stage_grid(c, (const void *)k1, B, ntiles));
     }
@@ -1799,10 +1805,10 @@ int launch_step(swe_ctx *c, long long step, double dt_fixed, const OverlapPlan &
     return SWE_OK;
 }
 
-int launch_step_any(swe_ctx *c, long long step, double dt_fixed)
+int launch_step_any(swe_ctx *c, long long step, double dt_fixed, bool phi_force = false)
 {
-    return c->cfg.precision == SWE_F64 ? launch_step<double>(c, step, dt_fixed)
-                                       : launch_step<float>(c, step, dt_fixed);
+    return c->cfg.precision == SWE_F64 ? launch_step<double>(c, step, dt_fixed, phi_force)
+                                       : launch_step<float>(c, step, dt_fixed, phi_force);
 }
 
 int health_status(swe_ctx *c)
@@ -1863,7 +1869,10 @@ int swe_create(const swe_config *cfg, swe_ctx **out)
         cfg->limiter < 0 || cfg->limiter > 4 || cfg->waf_limiter < 0 || cfg->waf_limiter > 2 ||
         cfg->cfl_rule < 0 || cfg->cfl_rule > 1 || !(cfg->g > 0) || !(cfg->cfl > 0) ||
         !(cfg->eps >= 0) || (cfg->waf_positivity != 0 && cfg->waf_positivity != 1) ||
-        (cfg->phi_in_stage != 0 && cfg->phi_in_stage != 1) || (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+        (cfg->phi_in_stage != 0 && cfg->phi_in_stage != 1) ||
+        (cfg->phi_every != 0 && cfg->phi_every != 1 && cfg->phi_every != 2 && cfg->phi_every != 3 &&
+         cfg->phi_every != 6) ||
+        (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
          cfg->block != 512) ||
         cfg->cell_kernel < 0 || cfg->cell_kernel > 1 ||
         (cfg->waves != 0 && cfg->waves != 6 && cfg->waves != 7) || (!cfg->alloc != !cfg->free))
@@ -2307,11 +2316,13 @@ int swe_step(swe_ctx *c, int n_steps, double dt_fixed)
             const int rc = ensure_graph(c, dt_fixed);
             if (rc != SWE_OK) return rc;
             HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
+            c->phi_stale = false;  // the chunk's first step evaluates phi
             c->step_count += kGraphSteps;
             done += kGraphSteps;
         } else {
-            int rc = launch_step_any(c, c->step_count, dt_fixed);
+            int rc = launch_step_any(c, c->step_count, dt_fixed, c->phi_stale);
             if (rc != SWE_OK) return rc;
+            c->phi_stale = false;
             c->step_count += 1;
             done += 1;
         }
@@ -2332,9 +2343,10 @@ int swe_step_overlap(swe_ctx *c, double dt_fixed, void *dev_sendbuf, void *pack_
     HIP_OK(c, hipEventRecord(c->ev0, c->stream));
     OverlapPlan ov;
     ov.sendbuf = dev_sendbuf;
-    const int rc = c->cfg.precision == SWE_F64 ? launch_step<double>(c, c->step_count, dt_fixed, ov)
-                                               : launch_step<float>(c, c->step_count, dt_fixed, ov);
+    const int rc = c->cfg.precision == SWE_F64 ? launch_step<double>(c, c->step_count, dt_fixed, c->phi_stale, ov)
+                                               : launch_step<float>(c, c->step_count, dt_fixed, c->phi_stale, ov);
     if (rc != SWE_OK) return rc;
+    c->phi_stale = false;
     if (pack_done_event) HIP_OK(c, hipEventRecord((hipEvent_t)pack_done_event, c->stream));
     c->step_count += 1;
     HIP_OK(c, hipEventRecord(c->ev1, c->stream));
@@ -2394,6 +2406,7 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
             (void)hipMemcpyAsync(Ucur, saveU, bytes, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
             c->step_count = step0;
+            c->phi_stale = true;
             rc = swe_step(c, 2, 0.0);  // warm-up
             if (rc != SWE_OK) break;
             rc = swe_step(c, n_steps, 0.0);
@@ -2415,6 +2428,7 @@ int swe_autotune(swe_ctx *c, int n_steps, int *block_out, int *grid_out)
     (void)hipMemcpyAsync(c->clock, saveK, clock_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);
     c->step_count = step0;
+    c->phi_stale = true;  // phi was overwritten by the candidates' runs
     dfree(c, saveU);
     dfree(c, saveK);
     if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }

@@ -414,17 +414,17 @@ struct swe_trainer {
 
 namespace swe {
 
-int launch_limiter_phi(swe_ctx *c, const void *U)
+int launch_limiter_phi(swe_ctx *c, const void *U, float *out)
 {
     if (!c->has_mlp) return err(c, SWE_ERR_STATE, "learned limiter weights not set");
     const int n = c->n_total, B = 256, G = (n + B - 1) / B;
     if (c->tsize == 8) {
         PhiArgs<double> a{n, (const int4 *)c->nbr, (const double4 *)c->he_co, (const double4 *)U,
-                          (const MlpDev *)c->mlp, c->phi, c->cfg.g, c->cfg.eps};
+                          (const MlpDev *)c->mlp, out, c->cfg.g, c->cfg.eps};
         hipLaunchKernelGGL(k_limiter_phi<double>, dim3(G), dim3(B), 0, c->stream, a);
     } else {
         PhiArgs<float> a{n, (const int4 *)c->nbr, (const float4 *)c->he_co, (const float4 *)U,
-                         (const MlpDev *)c->mlp, c->phi, (float)c->cfg.g, (float)c->cfg.eps};
+                         (const MlpDev *)c->mlp, out, (float)c->cfg.g, (float)c->cfg.eps};
         hipLaunchKernelGGL(k_limiter_phi<float>, dim3(G), dim3(B), 0, c->stream, a);
     }
     return hipGetLastError() == hipSuccess ? SWE_OK : err(c, SWE_ERR_DEVICE, "limiter launch failed");
@@ -445,6 +445,7 @@ int swe_limiter_set_weights(swe_ctx *c, const float *params)
     if (hipMemcpy(c->mlp, &w, sizeof(MlpDev), hipMemcpyHostToDevice) != hipSuccess)
         return err(c, SWE_ERR_DEVICE, "copy");
     c->has_mlp = true;
+    c->phi_stale = true;  // the next step evaluates phi with these weights
     return SWE_OK;
 }
 
@@ -453,12 +454,11 @@ int swe_limiter_phi(swe_ctx *c, float *dev_phi)
     if (!c || !dev_phi) return err(c, SWE_ERR_ARG, "null argument");
     if (!c->has_state) return err(c, SWE_ERR_STATE, "no state");
     if (hipSetDevice(c->dev) != hipSuccess) return err(c, SWE_ERR_DEVICE, "hipSetDevice");
-    int rc = launch_limiter_phi(c, c->U[c->step_count & 1]);
+    // straight into the caller's buffer: the phi that the steps between two
+    // evaluations reuse stays as it is
+    int rc = launch_limiter_phi(c, c->U[c->step_count & 1], dev_phi);
     if (rc != SWE_OK) return rc;
-    if (hipMemcpyAsync(dev_phi, c->phi, sizeof(float) * 3 * (size_t)c->n_total,
-                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-        return err(c, SWE_ERR_DEVICE, "copy");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return err(c, SWE_ERR_DEVICE, "sync");
     return SWE_OK;
 }
 

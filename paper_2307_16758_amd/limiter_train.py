@@ -51,9 +51,9 @@ class Pair:
     children: object        # torch int32 [4 n_coarse]
 
 
-def _solver(prep, sc, limiter=swe.MINMOD, weights=None, cfl=0.45):
+def _solver(prep, sc, limiter=swe.MINMOD, weights=None, cfl=0.45, phi_every=1):
     s = swe.Solver(precision=swe.F32, scheme=swe.MUSCL, integrator=swe.RK2, limiter=limiter,
-                   cfl=cfl)
+                   cfl=cfl, phi_every=phi_every)
     s.mesh_upload(prep.mesh)
     if sc.hydrograph is not None:
         s.set_bc_series(*sc.hydrograph)
@@ -188,14 +188,30 @@ def _descendants(coarse_prep, fine_prep, levels, n_fine_global):
     return g2l[f * gid[:, None] + np.arange(f)[None, :]]
 
 
-def evaluate_ladder(sc, weights, t_end, log=print):
+def _cost_at_error(out, name):
+    """The plain limiter's cost at run ``name``'s L1(h), interpolated log-log
+    between minmod on the coarse mesh and on the once-refined one (a bound
+    where the error lies outside that range)."""
+    e0, c0 = out["minmod"]["l1"], out["minmod"]["gpu_s_per_sim_s"]
+    e1, c1 = out["minmod_2x"]["l1"], out["minmod_2x"]["gpu_s_per_sim_s"]
+    el = out[name]["l1"]
+    if e1 < el <= e0 and e0 > e1:
+        w_ = (np.log(e0) - np.log(el)) / (np.log(e0) - np.log(e1))
+        return float(np.exp(np.log(c0) + w_ * (np.log(c1) - np.log(c0))))
+    if el <= e1:
+        return ">= " + repr(c1)
+    return "<= " + repr(c0)
+
+
+def evaluate_ladder(sc, weights, t_end, log=print, phi_every=()):
     """Equal-error comparison on nested meshes.  Reference: the scenario on
     the mesh refined twice (16 cells per coarse cell), restricted to the
     coarse mesh.  Runs: learned, minmod and van Albada on the coarse mesh, and
     minmod on the once-refined mesh (the next rung of the plain limiter's
     cost-error ladder), all restricted to the coarse mesh.  The plain
     limiter's cost at the learned limiter's error is interpolated log-log
-    between its two rungs."""
+    between its two rungs.  Each k in ``phi_every`` adds a learned run that
+    evaluates the network every k steps ("learned_every_k")."""
     from swe_inputs import refine_scenario
     s1 = refine_scenario(sc)
     s2 = refine_scenario(s1)
@@ -214,17 +230,18 @@ def evaluate_ladder(sc, weights, t_end, log=print):
     out = {}
     w_mc = np.zeros_like(weights)
     w_mc[-1] = 1e3            # phi = 1: the monotonized central limiter (TVD bound)
-    rungs = [("learned", pc, sc, swe.LEARNED, weights, 0),
-             ("phi1_mc", pc, sc, swe.LEARNED, w_mc, 0),
-             ("minmod", pc, sc, swe.MINMOD, None, 0),
-             ("vanalbada", pc, sc, swe.VANALBADA, None, 0),
-             ("minmod_2x", p1, s1, swe.MINMOD, None, 1)]
+    rungs = [("learned", pc, sc, swe.LEARNED, weights, 0, 1)]
+    rungs += [(f"learned_every_{k}", pc, sc, swe.LEARNED, weights, 0, k) for k in phi_every]
+    rungs += [("phi1_mc", pc, sc, swe.LEARNED, w_mc, 0, 1),
+              ("minmod", pc, sc, swe.MINMOD, None, 0, 1),
+              ("vanalbada", pc, sc, swe.VANALBADA, None, 0, 1),
+              ("minmod_2x", p1, s1, swe.MINMOD, None, 1, 1)]
     # one-time costs (code loading at a kernel's first launch) stay out of
     # the timed runs: every rung's kernels run once on a throwaway solver
-    for _, prep, scen, lim, w, _ in rungs:
-        _run_to(_solver(prep, scen, limiter=lim, weights=w), 1e-3)
-    for name, prep, scen, lim, w, lev in rungs:
-        s = _solver(prep, scen, limiter=lim, weights=w)
+    for _, prep, scen, lim, w, _, k in rungs:
+        _run_to(_solver(prep, scen, limiter=lim, weights=w, phi_every=k), 1e-3)
+    for name, prep, scen, lim, w, lev, k in rungs:
+        s = _solver(prep, scen, limiter=lim, weights=w, phi_every=k)
         try:
             gpu = _run_to(s, t_end)
         except swe.SweError as e:  # e.g. a depth below -eps: reported, not fatal
@@ -245,16 +262,9 @@ def evaluate_ladder(sc, weights, t_end, log=print):
                          gpu_s_per_sim_s=gpu / t_end, cells=prep.sub.n_total)
         log(f"  {name}: L1(h) {out[name]['l1']:.4e}  L1(eta, wet) {out[name]['l1_eta']:.4e}  "
             f"GPU s / sim s {gpu / t_end:.4e}")
-    e0, c0 = out["minmod"]["l1"], out["minmod"]["gpu_s_per_sim_s"]
-    e1, c1 = out["minmod_2x"]["l1"], out["minmod_2x"]["gpu_s_per_sim_s"]
-    el = out["learned"]["l1"]
-    if e1 < el <= e0 and e0 > e1:
-        w_ = (np.log(e0) - np.log(el)) / (np.log(e0) - np.log(e1))
-        out["minmod_cost_at_learned_error"] = float(np.exp(np.log(c0) + w_ * (np.log(c1) - np.log(c0))))
-    elif el <= e1:
-        out["minmod_cost_at_learned_error"] = ">= " + repr(c1)
-    else:
-        out["minmod_cost_at_learned_error"] = "<= " + repr(c0)
+    out["minmod_cost_at_learned_error"] = _cost_at_error(out, "learned")
+    for k in phi_every:
+        out[f"minmod_cost_at_learned_every_{k}_error"] = _cost_at_error(out, f"learned_every_{k}")
     return out
 
 
@@ -276,6 +286,10 @@ def main(argv=None):
     ap.add_argument("--kind", choices=("river", "dambreak"), default="river",
                     help="river: inflow into a lake at rest (config-4 recipe); dambreak: a 2 m "
                          "dam break at mid reach of the same channel (fronts)")
+    ap.add_argument("--phi-every", type=int, nargs="*", default=[], choices=(2, 3, 6),
+                    help="also run the learned limiter with the network evaluated every k steps")
+    ap.add_argument("--params", default="",
+                    help="JSON file of an earlier run (its 'params'): skip the training")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
     rng = np.random.default_rng(4)
@@ -288,14 +302,21 @@ def main(argv=None):
         return river_channel(Lx=10000.0, Ly=2000.0, nx=a.nx, ny=a.ny, seed=seed, inflow_q=q)
 
     tr = [scen(1000 + i) for i in range(a.train)]
-    snaps = list(np.linspace(a.t_end / 4, a.t_end, 4))
-    params, hist, _ = run_pipeline(tr, [], refine_scenario, snaps, a.t_end, epochs=a.epochs)
+    if a.params:
+        # the same draws of the generator as a training run, so that the
+        # held-out scenarios are the same
+        with open(a.params) as f:
+            params = np.asarray(json.load(f)["params"], np.float32)
+        hist = []
+    else:
+        snaps = list(np.linspace(a.t_end / 4, a.t_end, 4))
+        params, hist, _ = run_pipeline(tr, [], refine_scenario, snaps, a.t_end, epochs=a.epochs)
     out = dict(kind=a.kind, train=a.train, nx=a.nx, ny=a.ny, t_end=a.t_end, loss_history=hist,
                held_out=[])
     for i in range(a.held_out):
         sc = scen(1180 + i)
         print(f"held-out scenario {1180 + i}", flush=True)
-        res = evaluate_ladder(sc, params, a.t_end)
+        res = evaluate_ladder(sc, params, a.t_end, phi_every=tuple(a.phi_every))
         out["held_out"].append(dict(seed=1180 + i, inflow_q=sc.inflow_q, **res))
         print(json.dumps(out["held_out"][-1]), flush=True)
     if a.out:

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # compiled with different flags for a measurement)
 LIB_PATH = os.environ.get("SWE_LIBRARY", os.path.join(HERE, "libswe.so"))
 
-SWE_ABI_VERSION = 4
+SWE_ABI_VERSION = 5
 SWE_OK = 0
 ERRORS = {-1: "SWE_ERR_ARG", -2: "SWE_ERR_MESH", -3: "SWE_ERR_STATE", -4: "SWE_ERR_NONFINITE",
           -5: "SWE_ERR_NEGATIVE_DEPTH", -6: "SWE_ERR_DEVICE", -7: "SWE_ERR_OOM",
@@ -69,7 +69,7 @@ class swe_config(C.Structure):
                 ("cfl_rule", C.c_int), ("device", C.c_int), ("g", C.c_double),
                 ("cfl", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
                 ("block", C.c_int), ("cell_kernel", C.c_int), ("stream", C.c_void_p),
-                ("waves", C.c_int), ("reserved0", C.c_int), ("alloc", ALLOC_FN),
+                ("waves", C.c_int), ("phi_every", C.c_int), ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("waf_positivity", C.c_int),
                 ("phi_in_stage", C.c_int)]
 

@@ -173,7 +173,8 @@ def _status(fn, *args):
 
 def test_size_limits_and_call_order():
     swe, prepare_scenario = lib()
-    for bad in (dict(waves=5), dict(block=96), dict(cell_kernel=2)):
+    for bad in (dict(waves=5), dict(block=96), dict(cell_kernel=2), dict(phi_every=4),
+                dict(phi_every=-1)):
         with pytest.raises(swe.SweError) as e:
             swe.Solver(precision=0, **bad)
         assert e.value.code == ARG

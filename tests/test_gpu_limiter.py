@@ -92,6 +92,95 @@ def test_learned_limiter_steps(prec, tol):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 1e-3)])
+@pytest.mark.parametrize("pe", [2, 3, 6])
+def test_phi_every_matches_oracle(prec, tol, pe):
+    """phi evaluated every pe steps (phi_every) against the oracle on the same
+    schedule, 50 steps (graph chunks of six steps and two single steps); the
+    every-step oracle run differs from both by more than the tolerance, so the
+    schedule is what is being compared."""
+    sc = small_river()
+    h, hu, hv = flowing_state(sc)
+    sc.h, sc.hu, sc.hv = h, hu, hv
+    w = params(1)
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=prec, limiter=3, phi_every=pe)
+    s.limiter_set_weights(w)
+    l2g = pr.sub.l2g
+    par.limiter = O.LEARNED
+    par.mlp = bf16_round(w)
+    par.mlp_bf16 = 1
+    dt = M.dt(par, h[l2g], hu[l2g], hv[l2g])
+    s.step(50, dt)
+    gst = s.read_state()
+    par.phi_every = pe
+    r = M.run(par, h[l2g], hu[l2g], hv[l2g], 50, dt_fixed=dt)
+    par.phi_every = 1
+    r1 = M.run(par, h[l2g], hu[l2g], hv[l2g], 50, dt_fixed=dt)
+    errs = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(gst, r[:3])]
+    sep = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(r1[:3], r[:3])]
+    print("phi every", pe, prec, errs, "every step vs schedule", sep)
+    assert max(errs) <= tol
+    assert max(sep) > 2 * tol
+
+
+@pytest.mark.parametrize("pis", [0, 1])
+def test_phi_every_launch_paths_agree(pis):
+    """With phi_every = 3 the schedule follows the step index since
+    set_state on every launch path: a graph-replayed run, single steps, and a
+    run started off the graph's alignment give bitwise the same state; new
+    weights make the next step evaluate phi (equal to a fresh run with those
+    weights from the same state), and reading phi with swe_limiter_phi between
+    evaluations leaves the run unchanged."""
+    import torch
+    sc = small_river()
+    h, hu, hv = flowing_state(sc)
+    sc.h, sc.hu, sc.hv = h, hu, hv
+    w1, w2 = params(1), params(2)
+    swe, prepare_scenario = lib()
+    pr = prepare_scenario(sc)
+    l2g = pr.sub.l2g
+    M, _ = O.global_mesh(sc)
+    dt = 0.5 * M.dt(O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2), h, hu, hv)
+
+    def solver(w, state=None, t=0.0):
+        s, _, _, _ = make_pair(sc, "muscl_minmod_rk2", precision=0, prepared=pr, limiter=3,
+                               phi_every=3, phi_in_stage=pis)
+        s.limiter_set_weights(w)
+        if state is not None:
+            s.set_state(*state, t=t)
+        return s
+
+    a = solver(w1)
+    a.step(24, dt)                       # four graph chunks
+    b = solver(w1)
+    for _ in range(24):
+        b.step(1, dt)                    # single launches
+    c = solver(w1)
+    c.step(1, dt)
+    c.step(2, dt)
+    c.step(21, dt)                       # singles, then chunks from step 6 on
+    d = solver(w1)
+    d.step(4, dt)
+    buf = torch.empty(3 * pr.sub.n_total, dtype=torch.float32, device="cuda")
+    d.limiter_phi(buf)                   # between evaluations (steps 3 and 6)
+    d.step(20, dt)
+    ref = a.read_state()
+    for s_ in (b, c, d):
+        assert all(np.array_equal(x, y) for x, y in zip(s_.read_state(), ref))
+    # new weights at step 4 (between evaluations): evaluated at once
+    e = solver(w1)
+    e.step(4, dt)
+    mid, t_mid = e.read_state(), e.time()
+    e.limiter_set_weights(w2)
+    e.step(2, dt)
+    f = solver(w2, state=mid, t=t_mid)
+    f.step(2, dt)
+    assert all(np.array_equal(x, y) for x, y in zip(e.read_state(), f.read_state()))
+    g_ = solver(w1, state=mid, t=t_mid)
+    g_.step(2, dt)
+    assert not np.array_equal(g_.read_state()[1], f.read_state()[1])
+
+
 @pytest.mark.parametrize("prec,integ,block,P", [(0, 1, 256, 1), (1, 1, 256, 1), (0, 0, 256, 1),
                                                  (0, 1, 64, 1), (0, 1, 512, 1), (0, 1, 256, 4)])
 def test_network_in_stage_equals_separate_kernel(prec, integ, block, P):

@@ -479,3 +479,45 @@ def test_learned_limiter_mirror_symmetry():
     np.testing.assert_allclose(h, h[pair], rtol=0, atol=1e-11)
     np.testing.assert_allclose(hu, -hu[pair], rtol=0, atol=1e-11)
     np.testing.assert_allclose(hv, hv[pair], rtol=0, atol=1e-11)
+
+
+def test_learned_limiter_phi_every():
+    """phi evaluated every k steps of a run (k = phi_every), reused between.
+    A network whose output does not depend on its inputs gives the same phi
+    at every step, so on an all-wet reach (eligibility fixed) every k gives
+    bitwise the same run: a step between evaluations that fell back to
+    another limiter, or read another step's buffer, breaks this.  With a
+    network that does depend on the state, k > 1 changes the result, and the
+    schedule counts steps from the start of the run: 6 + 6 steps with k = 3
+    restarted on the schedule equal 12 steps, 5 + 7 do not."""
+    sc = strip_riemann(L=10.0, W=2.0, nx=30, ny=6, hL=1.2, hR=0.6, uL=0.3, uR=-0.2,
+                       ends=BC_WALL)
+    sc.hv = sc.h * 0.1
+    M, _ = O.global_mesh(sc)
+    p = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2, limiter=O.LEARNED)
+    const = np.zeros(O.MLP_NPAR)
+    const[-1] = 0.3                       # phi = sigmoid(0.3) wherever evaluated
+    p.mlp = const
+    runs = {}
+    for k in (0, 1, 2, 3, 6):
+        p.phi_every = k
+        runs[k] = M.run(p, sc.h, sc.hu, sc.hv, 24, dt_fixed=0.01)[:3]
+    for k in (0, 2, 3, 6):
+        assert all(np.array_equal(a, b) for a, b in zip(runs[k], runs[1])), k
+    # the constant phi is used: the run differs from minmod's
+    pm = O.scenario_params(sc, scheme=O.MUSCL, integrator=O.RK2)
+    mm = M.run(pm, sc.h, sc.hu, sc.hv, 24, dt_fixed=0.01)[:3]
+    assert np.abs(mm[1] - runs[1][1]).max() > 1e-6
+
+    p.mlp = np.random.default_rng(5).normal(0.0, 0.5, O.MLP_NPAR)
+    p.phi_every = 1
+    r1 = M.run(p, sc.h, sc.hu, sc.hv, 12, dt_fixed=0.01)[:3]
+    p.phi_every = 3
+    r3 = M.run(p, sc.h, sc.hu, sc.hv, 12, dt_fixed=0.01)[:3]
+    assert np.abs(r3[1] - r1[1]).max() > 1e-6
+    half = M.run(p, sc.h, sc.hu, sc.hv, 6, dt_fixed=0.01)[:3]
+    r66 = M.run(p, *half, 6, dt_fixed=0.01)[:3]
+    assert all(np.array_equal(a, b) for a, b in zip(r66, r3))
+    five = M.run(p, sc.h, sc.hu, sc.hv, 5, dt_fixed=0.01)[:3]
+    r57 = M.run(p, *five, 7, dt_fixed=0.01)[:3]
+    assert np.abs(r57[1] - r3[1]).max() > 1e-9
