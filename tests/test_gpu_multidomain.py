@@ -12,7 +12,8 @@ the steps every owned cell equals the undecomposed run's cell bit for bit.
   HLLC-RK2 (stencil radius 4: one step per exchange);
 * the 999,824-cell river split into 8 parts, k = 4, WAF (radius 2: two
   steps per exchange) and first-order HLLC (radius 1: four steps), and
-  MUSCL-RK2 with the superbee, van Albada and learned limiters.
+  MUSCL-RK2 with the superbee, van Albada and learned limiters (the last
+  also with the network every third step).
 """
 import time
 
@@ -58,11 +59,11 @@ def _combined_dt(local):
     return 0.0 if np.isinf(m) else m
 
 
-def _decomposed_vs_global(sc, name, P, k, per, rounds, limiter=None, weights=None):
+def _decomposed_vs_global(sc, name, P, k, per, rounds, limiter=None, weights=None, phi_every=1):
     import torch
     swe, prepare_scenario = lib()
     stream = torch.cuda.current_stream()
-    kw = dict(SCHEME_KW[name], precision=0, stream=stream)
+    kw = dict(SCHEME_KW[name], precision=0, stream=stream, phi_every=phi_every)
     if limiter is not None:
         kw["limiter"] = limiter
     nbr = swe.swe_dual_graph(sc.mesh.n_nodes, sc.mesh.tri)
@@ -149,3 +150,14 @@ def test_config2_eight_parts_other_limiters(limiter):
         w = np.random.default_rng(5).normal(0.0, 0.3, O.MLP_NPAR).astype(np.float32)
     _decomposed_vs_global(config2(), "muscl_minmod_rk2", P=8, k=4, per=1, rounds=3,
                           limiter=limiter, weights=w)
+
+
+def test_config2_eight_parts_learned_phi_every():
+    """The learned limiter with the network every third step: the parts
+    evaluate phi on the same steps as the undecomposed run (steps 0 and 3
+    of four), from ghost layers the last exchange refreshed, and reuse it
+    on the steps between, so owned cells still match bitwise."""
+    from oracle import oracle as O
+    w = np.random.default_rng(5).normal(0.0, 0.3, O.MLP_NPAR).astype(np.float32)
+    _decomposed_vs_global(config2(), "muscl_minmod_rk2", P=8, k=4, per=1, rounds=4,
+                          limiter=3, weights=w, phi_every=3)

@@ -115,3 +115,40 @@ def test_overlap_rejects_missing_buffer_and_works_without_ghosts():
     ev.synchronize()
     for x, y in zip(g.read_state(), h.read_state()):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("pis", [0, 1])
+def test_overlap_steps_with_learned_phi_every(pis):
+    """The learned limiter with the network every third step: overlapped
+    steps evaluate phi on the same steps as plain ones (the step index since
+    set_state), so seven overlapped steps give bitwise the state and send
+    buffer of seven plain steps, each followed by a pack."""
+    import torch
+    from oracle import oracle as O
+    swe, prepare_scenario = lib()
+    sc = wavy_scenario()
+    w = np.random.default_rng(5).normal(0.0, 0.3, O.MLP_NPAR).astype(np.float32)
+    pr = prepare_scenario(sc, P=3, p=1, k=4)
+    kw = dict(precision=0, prepared=pr, limiter=3, phi_every=3, phi_in_stage=pis)
+    a, _, _, _ = make_pair(sc, "muscl_minmod_rk2", **kw)
+    b, _, _, _ = make_pair(sc, "muscl_minmod_rk2", **kw)
+    c, _, _, _ = make_pair(sc, "muscl_minmod_rk2", **dict(kw, phi_every=1))
+    for s in (a, b, c):
+        s.limiter_set_weights(w)
+    n_send, _ = a.ghost_sizes()
+    ba = torch.empty(3 * n_send, dtype=torch.float32, device="cuda")
+    bb = torch.empty_like(ba)
+    for _ in range(7):
+        a.step(1, 0.02)
+        a.pack_ghosts(ba)
+        b.step_overlap(bb, 0.02)
+        c.step(1, 0.02)
+    a.sync()
+    b.sync()
+    sa, sb = a.read_state(), b.read_state()
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+    assert np.array_equal(ba.cpu().numpy(), bb.cpu().numpy())
+    # the schedule is in effect: every-step evaluation gives another state
+    assert not np.array_equal(c.read_state()[1], sa[1])
+    for s in (a, b, c):
+        s.close()
