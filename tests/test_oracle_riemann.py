@@ -212,3 +212,4 @@ def test_van_albada_values():
     for a, b in rng.normal(size=(2000, 2)) * np.exp(rng.normal(size=(2000, 2))):
         assert O.limiter(O.VANALBADA, a, b) == pytest.approx(van_albada_ratio_form(a, b),
                                                              rel=1e-13, abs=1e-300)
+
