@@ -250,6 +250,10 @@ def main():
                     help="sub-domain workloads: each step with the high-overlap schedule "
                          "(swe_step_overlap: send cells' tiles, pack on a side stream while the "
                          "other tiles run) instead of a step followed by a pack")
+    ap.add_argument("--exchange-every", type=int, default=0, metavar="M",
+                    help="sub-domain workloads: steps per exchange (pack and unpack); 0: the "
+                         "most the ghost layers allow, k // r for stencil radius r per step "
+                         "(4 MUSCL-RK2, 2 WAF, 1 first-order HLLC)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for the HBM byte counters)")
@@ -332,6 +336,17 @@ def main():
                                        .astype(np.float32)).cuda()
             torch.cuda.synchronize()
 
+    exch = 1          # steps per exchange interval
+    if sendbuf is not None:
+        radius = 4 if kw["integrator"] == 1 else (2 if kw["scheme"] != 0 else 1)
+        exch = args.exchange_every if args.exchange_every > 0 else max(1, k // radius)
+        if exch * radius > k:
+            raise SystemExit(f"{k} ghost layers allow at most {max(1, k // radius)} steps per exchange")
+
+    def whole(n):
+        """n rounded up to whole exchange intervals."""
+        return exch * -(-n // exch)
+
     tuned = s.autotune(10) if args.autotune else None
     s.step(args.warmup)
     if args.snapshot_every > 0:
@@ -366,13 +381,15 @@ def main():
             s.step(nsteps)
             s.sync()
         elif args.overlap:
-            for _ in range(nsteps):     # one step per exchange interval, pack overlapped
+            for _ in range(nsteps // exch):   # per exchange interval, the last step's pack overlapped
+                if exch > 1:
+                    s.step(exch - 1)
                 s.step_overlap(sendbuf)
                 s.unpack_ghosts(recvbuf)
             s.sync()
         else:
-            for _ in range(nsteps):     # one step per exchange interval: step, pack, unpack
-                s.step(1)
+            for _ in range(nsteps // exch):   # per exchange interval: steps, pack, unpack
+                s.step(exch)
                 s.pack_ghosts(sendbuf)
                 s.unpack_ghosts(recvbuf)
             s.sync()
@@ -382,9 +399,9 @@ def main():
 
     # one untimed run of K steps sizes the timed runs: K steps repeated
     # until a run lasts at least min_run_ms
-    w0, _ = one_run(args.steps)
+    w0, _ = one_run(whole(args.steps))
     reps = max(1, int(np.ceil(args.min_run_ms * 1e-3 / max(w0, 1e-9))))
-    per_run = args.steps * reps
+    per_run = whole(args.steps * reps)
     runs = [one_run(per_run) for _ in range(args.runs)]
     walls = sorted(r[0] for r in runs)
     wall = walls[len(walls) // 2]
@@ -429,7 +446,8 @@ def main():
                                + (", learned limiter" if args.limiter == "learned" else "")
                                + (f" (network every {args.phi_every} steps)"
                                   if args.limiter == "learned" and args.phi_every > 1 else "")
-                               + (f", part of {P} with {k} ghost layers + pack and unpack"
+                               + (f", part of {P} with {k} ghost layers + pack and unpack every "
+                                  + (f"{exch} steps" if exch > 1 else "step")
                                   + (" (high-overlap steps)" if args.overlap else "") if P > 1 else "")
                                + (f", snapshot to host every {args.snapshot_every} steps"
                                   if args.snapshot_every > 0 else ""),
