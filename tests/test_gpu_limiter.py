@@ -92,18 +92,21 @@ def test_learned_limiter_steps(prec, tol):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("cell", [0, 1])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 1e-3)])
 @pytest.mark.parametrize("pe", [2, 3, 6])
-def test_phi_every_matches_oracle(prec, tol, pe):
+def test_phi_every_matches_oracle(prec, tol, pe, cell):
     """phi evaluated every pe steps (phi_every) against the oracle on the same
-    schedule, 50 steps (graph chunks of six steps and two single steps); the
-    every-step oracle run differs from both by more than the tolerance, so the
-    schedule is what is being compared."""
+    schedule, 50 steps (graph chunks of six steps and two single steps), with
+    the tiled and the one-thread-per-cell stage kernels; the every-step oracle
+    run differs from both by more than the tolerance, so the schedule is what
+    is being compared."""
     sc = small_river()
     h, hu, hv = flowing_state(sc)
     sc.h, sc.hu, sc.hv = h, hu, hv
     w = params(1)
-    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=prec, limiter=3, phi_every=pe)
+    s, M, par, pr = make_pair(sc, "muscl_minmod_rk2", precision=prec, limiter=3, phi_every=pe,
+                              cell_kernel=cell)
     s.limiter_set_weights(w)
     l2g = pr.sub.l2g
     par.limiter = O.LEARNED
@@ -118,7 +121,7 @@ def test_phi_every_matches_oracle(prec, tol, pe):
     r1 = M.run(par, h[l2g], hu[l2g], hv[l2g], 50, dt_fixed=dt)
     errs = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(gst, r[:3])]
     sep = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(r1[:3], r[:3])]
-    print("phi every", pe, prec, errs, "every step vs schedule", sep)
+    print("phi every", pe, prec, cell, errs, "every step vs schedule", sep)
     assert max(errs) <= tol
     assert max(sep) > 2 * tol
 
