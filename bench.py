@@ -94,6 +94,18 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def exchange_interval(kw, k, requested=0):
+    """Steps per exchange of a sub-domain with k ghost layers: a step reads
+    r layers (4 for MUSCL-RK2, 2 for MUSCL-Euler and WAF, 1 for first-order
+    HLLC), so k layers last k // r steps; ``requested`` (> 0) asks for a
+    shorter interval."""
+    radius = 4 if kw["integrator"] == 1 else (2 if kw["scheme"] != 0 else 1)
+    most = max(1, k // radius)
+    if requested > most:
+        raise SystemExit(f"{k} ghost layers allow at most {most} steps per exchange")
+    return requested if requested > 0 else most
+
+
 def kernel_source_hash():
     """sha256 of the device sources (the .hip files and the headers they
     include; the host toolkit, .cpp built by g++, holds no device code): a
@@ -336,12 +348,7 @@ def main():
                                        .astype(np.float32)).cuda()
             torch.cuda.synchronize()
 
-    exch = 1          # steps per exchange interval
-    if sendbuf is not None:
-        radius = 4 if kw["integrator"] == 1 else (2 if kw["scheme"] != 0 else 1)
-        exch = args.exchange_every if args.exchange_every > 0 else max(1, k // radius)
-        if exch * radius > k:
-            raise SystemExit(f"{k} ghost layers allow at most {max(1, k // radius)} steps per exchange")
+    exch = exchange_interval(kw, k, args.exchange_every) if sendbuf is not None else 1
 
     def whole(n):
         """n rounded up to whole exchange intervals."""

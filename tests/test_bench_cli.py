@@ -30,3 +30,21 @@ def test_traffic_is_dropped_when_kernels_change(tmp_path, monkeypatch):
     assert b.measured_traffic("demo", "k_stage") == 123.0
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 64)
     assert b.measured_traffic("demo", "k_stage") is None
+
+
+def test_exchange_interval_follows_the_ghost_layers():
+    import importlib.util
+    import pytest
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    muscl_rk2 = dict(scheme=1, integrator=1)
+    waf = dict(scheme=2, integrator=0)
+    hllc1 = dict(scheme=0, integrator=0)
+    assert b.exchange_interval(muscl_rk2, 4) == 1
+    assert b.exchange_interval(waf, 4) == 2
+    assert b.exchange_interval(hllc1, 4) == 4
+    assert b.exchange_interval(hllc1, 4, requested=1) == 1
+    assert b.exchange_interval(dict(scheme=1, integrator=0), 4) == 2
+    with pytest.raises(SystemExit):
+        b.exchange_interval(waf, 4, requested=3)
