@@ -8,7 +8,8 @@
   on-device pack gathers exactly the send lists.
 * The 64-scenario ensemble (38.1M cells in one context): the smallest, the
   median and the largest scenario equal their separate runs bitwise (state
-  and clock) after 10 CFL steps, and the smallest one follows the oracle.
+  and clock) after 100 CFL steps, and the smallest and the median one
+  follow the oracle (1e-4 per field, their clocks to 1e-5).
 """
 import numpy as np
 import pytest
@@ -82,7 +83,7 @@ def test_config5_ensemble():
                 np.concatenate([x.hu[p.sub.l2g] for x, p in zip(scs, preps)]),
                 np.concatenate([x.hv[p.sub.l2g] for x, p in zip(scs, preps)]))
     assert s.offsets[-1] == sum(x.n_cells for x in scs)
-    s.step(10)
+    s.step(100)
     bst = s.read_state()
     times = s.scenario_times()
     off = s.offsets
@@ -95,22 +96,25 @@ def test_config5_ensemble():
         if x.hydrograph is not None:
             one.set_bc_series(*x.hydrograph)
         one.set_state(x.h[p.sub.l2g], x.hu[p.sub.l2g], x.hv[p.sub.l2g])
-        one.step(10)
+        one.step(100)
         st = one.read_state()
         sl = slice(off[i], off[i + 1])
         for f in range(3):
             assert np.array_equal(bst[f][sl], st[f]), (i, f)
         assert times[i] == one.time()
         one.close()
-    i = int(order[0])
-    x, p = scs[i], preps[i]
-    l2g = p.sub.l2g
-    M, osub = oracle_side(x)
-    assert_same_numbering(p.sub, osub)
-    par = O.scenario_params(x, scheme=1, integrator=1, limiter=0)
-    r = M.run(par, x.h[l2g], x.hu[l2g], x.hv[l2g], 10)
-    sl = slice(off[i], off[i + 1])
-    errs = state_errors([b[sl] for b in bst], r[:3], p.sub.n_owned)
-    print("ensemble, smallest scenario", x.n_cells, "cells, 10 CFL steps, rel errors", errs)
-    assert max(errs) <= 1e-4, errs
-    assert times[i] == pytest.approx(r[3], rel=1e-5)
+    # the smallest and the median scenario against the oracle (each with its
+    # own CFL steps)
+    for i in (int(order[0]), int(order[len(order) // 2])):
+        x, p = scs[i], preps[i]
+        l2g = p.sub.l2g
+        M, osub = oracle_side(x)
+        assert_same_numbering(p.sub, osub)
+        par = O.scenario_params(x, scheme=1, integrator=1, limiter=0)
+        r = M.run(par, x.h[l2g], x.hu[l2g], x.hv[l2g], 100)
+        sl = slice(off[i], off[i + 1])
+        errs = state_errors([b[sl] for b in bst], r[:3], p.sub.n_owned)
+        print("ensemble scenario", i, x.n_cells, "cells, 100 CFL steps, rel errors", errs,
+              "time", times[i], r[3])
+        assert max(errs) <= 1e-4, errs
+        assert times[i] == pytest.approx(r[3], rel=1e-5)
